@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for the inverse-DFT hot path — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package. The GPU library never calls it, links it or reads its
+output at run time, and this package never imports the GPU library.
+
+It computes, by plain and slow means, the discrete quantities of the paper's
+finite-element inverse DFT (Sec. 2 and Sec. 3.2):
+
+* ``fe``      — 1-D spectral-element tables (Eq. 12, GLL nodes, Sec. 3.2.1) and the
+                3-D standard-form Kohn-Sham operator (Eqs. 17 and 19), both as an
+                assembled sparse matrix and as Kronecker-factored 1-D applies.
+* ``ks``      — forward eigenproblem (Eq. 19), density (Eq. 4), loss (Eq. 1),
+                adjoint right-hand side and solution (Eqs. 7, 10, 20), gradient
+                (Eqs. 11, 22), central finite differences, L-BFGS (Eq. 21).
+* ``chfsi``   — the Chebyshev filter polynomial and Rayleigh-Ritz projection
+                (Sec. 3.2.2, Eqs. 23-24) by their plain definitions.
+
+Every function states the passage it follows. Nothing here is blocked, fused
+or reordered beyond what the definition states.
+"""

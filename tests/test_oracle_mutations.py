@@ -1,0 +1,79 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case patches one plausible slip into the oracle (a dropped factor, a
+transposed Kronecker factor, a flipped sign, a missing weight) and checks that
+the pin meant for it fails. This guards the pins themselves.
+"""
+import numpy as np
+import pytest
+
+from oracle import fe, ks
+from synth import workload
+
+
+def _kinetic_energy_ratio(p=3, n=2, L=2.0):
+    m = fe.mesh3d(p, n, L)
+    X = m.coords()
+    u = np.prod(L * L - X * X, axis=1)
+    ut = np.sqrt(m.weights()) * u
+    return ut @ fe.kinetic_apply(m, ut) / (1024.0 * L ** 13 / 225.0)
+
+
+def test_pin_catches_dropped_half(monkeypatch):
+    assert abs(_kinetic_energy_ratio() - 1) < 1e-12
+    orig = fe.kinetic_apply
+    monkeypatch.setattr(fe, "kinetic_apply", lambda m, X: 2.0 * orig(m, X))
+    assert abs(_kinetic_energy_ratio() - 1) > 0.5
+
+
+def test_pin_catches_transposed_factor(monkeypatch):
+    """One term with its stiffness factor on y instead of x."""
+    def bad(mesh, X):
+        m = mesh.m1
+        n1 = mesh.n1
+        s = 1.0 / np.sqrt(m.W1)
+        Ks = s[:, None] * m.K1 * s[None, :]
+        Ms = s[:, None] * m.Mc * s[None, :]
+        T = X.reshape(n1, n1, n1, -1)
+        t1 = fe._along(Ms, fe._along(Ks, fe._along(Ms, T, 2), 1), 0)   # slip: was x
+        t2 = fe._along(Ms, fe._along(Ks, fe._along(Ms, T, 2), 1), 0)
+        t3 = fe._along(Ks, fe._along(Ms, fe._along(Ms, T, 2), 1), 0)
+        return (0.5 * (t1 + t2 + t3)).reshape(X.shape)
+
+    m = fe.mesh3d(3, 2, 2.0)
+    X = np.random.default_rng(0).standard_normal((m.n_free, 2))
+    good = fe.kinetic_csr(m) @ X
+    assert np.abs(fe.kinetic_apply(m, X) - good).max() < 1e-12 * np.abs(good).max()
+    assert np.abs(bad(m, X) - good).max() > 1e-3 * np.abs(good).max()
+
+
+def _grad_fd_mismatch():
+    wl = workload(2, p=2, n=3, half_width=4.0)
+    m = fe.mesh3d(2, 3, 4.0)
+    X = m.coords()
+    vf, vs = wl.v_fixed(X), wl.v_xc_target(X)
+    rho_d, _ = ks.target_density(m, vf + vs, wl.n_elec)
+    u = 0.5 * np.sin(X[:, 0])
+    ev = ks.evaluate(m, vf + u, rho_d, wl.n_elec, method="bordered")
+    d = np.random.default_rng(1).standard_normal(m.n_free)
+    fd = ks.fd_directional(m, vf + u, rho_d, wl.n_elec, d, 1e-4)
+    return abs(ev.grad @ d - fd) / abs(fd)
+
+
+def test_pin_catches_adjoint_sign(monkeypatch):
+    assert _grad_fd_mismatch() < 1e-6
+    orig = ks.adjoint_rhs
+    monkeypatch.setattr(ks, "adjoint_rhs", lambda *a: -orig(*a))
+    assert _grad_fd_mismatch() > 0.5
+
+
+def test_pin_catches_missing_weight(monkeypatch):
+    wl = workload(2, p=3, n=2, half_width=4.0)
+    m = fe.mesh3d(3, 2, 4.0)
+    X = m.coords()
+    fw = ks.forward(m, wl.v_fixed(X), wl.n_occ, dense=True)
+    occ = ks.occupations(wl.n_elec)
+    W = m.weights()
+    assert abs(ks.electron_count(ks.density(fw.psi, occ, W), W) - wl.n_elec) < 1e-12
+    monkeypatch.setattr(ks, "density", lambda psi, occ, W: psi[:, :occ.size] ** 2 @ occ)
+    assert abs(ks.electron_count(ks.density(fw.psi, occ, W), W) - wl.n_elec) > 1e-3
