@@ -1,0 +1,205 @@
+/*
+ * invdft.h — C ABI of the MI355X (gfx950) inverse-DFT hot path.
+ *
+ * The library solves the discrete problems of finite-element inverse DFT:
+ * the standard-form Kohn-Sham eigenproblem H~ psi~ = eps psi~ (Eq. 19), the
+ * adjoint equations (H~ - eps_i) q_i = b_i with q_i orthogonal to the occupied
+ * orbitals (Eqs. 7, 10, 20 and the null-space treatment of Sec. 3.2.2), the
+ * density and loss (Eqs. 1, 4) and the gradient with respect to the nodal
+ * exchange-correlation potential (Eqs. 11, 22).
+ *
+ * Discretisation: box [-L, L]^3 with n x n x n hexahedral cells of order-p
+ * spectral elements (tensor-product Lagrange polynomials on Gauss-Lobatto-
+ * Legendre nodes, Eq. 12, Sec. 3.2.1). Homogeneous Dirichlet boundary; the
+ * unknowns are the N_f = (p n - 1)^3 interior nodes, numbered
+ *     a = (gx - 1) + n1 * ((gy - 1) + n1 * (gz - 1)),  n1 = p n - 1,
+ * with 1-D global node g = e p + j of cell e. The stiffness is integrated
+ * exactly, the overlap M is lumped by GLL quadrature into W = diag(W_a), and
+ * the potential is collocated at the nodes, so
+ *     H~ = (1/2) W^{-1/2} K W^{-1/2} + diag(v).
+ *
+ * Layout ("node-major", Sec. 3.2.3 and Fig. 4a): a block X of nv vectors is
+ * stored as X[a * ld + j], a in [0, N_f), j in [0, nv), ld >= nv: all
+ * coefficients of one basis function are contiguous.
+ *
+ * Pointers: every array argument is DEVICE memory unless its name ends in _h
+ * (host memory). The caller owns every buffer it passes; the library keeps no
+ * pointer after a call returns. The library owns only the mesh handle and the
+ * small device tables inside it (fe_mesh_destroy frees them). Buffers must be
+ * 16-byte aligned.
+ *
+ * Streams: all device work is enqueued on `stream` (a hipStream_t, NULL for
+ * the default stream). Calls that return host results (names ending in _h)
+ * synchronise that stream before returning. A mesh is immutable after
+ * creation, so calls on different streams with separate work buffers may run
+ * concurrently.
+ *
+ * Precision: FE_F64 -> double blocks and FP64 arithmetic. FE_F32 -> float
+ * blocks, FP32 arithmetic. FE_BF16 is accepted where stated: float blocks, the
+ * kinetic contraction rounded to bfloat16 (round to nearest even) with FP32
+ * accumulation. Potentials, weights, densities, Gram matrices, eigenvalues and
+ * every reduction are always FP64.
+ *
+ * Errors: a non-zero fe_status never aborts the process; fe_last_error()
+ * returns a thread-local message describing the last failure of this thread.
+ * On error, outputs are undefined except where stated for FE_ENOCONV,
+ * FE_ENOTPD and FE_EGAP.
+ */
+#ifndef INVDFT_H
+#define INVDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fe_mesh_s* fe_mesh;
+
+typedef enum {
+  FE_OK = 0,
+  FE_EINVAL = 1,   /* invalid argument (sizes, null or misaligned pointers, unknown op) */
+  FE_ENOMEM = 2,   /* device or host allocation failed */
+  FE_EDEVICE = 3,  /* HIP runtime error (message in fe_last_error) */
+  FE_ENOCONV = 4,  /* iteration limit reached; outputs hold the last iterate */
+  FE_ENOTPD = 5,   /* Cholesky of an overlap matrix failed; block left unchanged */
+  FE_EGAP = 6      /* no gap at the Fermi level: eps[nocc] - eps[nocc-1] < 1e-6 Ha */
+} fe_status;
+
+typedef enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 } fe_prec;
+
+/* Operation codes for fe_workspace_bytes. */
+typedef enum {
+  FE_OP_KS_APPLY = 0,
+  FE_OP_CHEB_FILTER = 1,
+  FE_OP_RAYLEIGH_RITZ = 2,
+  FE_OP_ADJOINT_SOLVE = 3,
+  FE_OP_LOSS_GRAD = 4,
+  FE_OP_EIGENSOLVE = 5
+} fe_op;
+
+/* ------------------------------------------------------------------ mesh --
+ * Build the mesh tables (Eq. 12 Lagrange basis on GLL nodes; exact-Gauss
+ * element stiffness and mass of Eq. 17; GLL-lumped W of Sec. 3.2.1) and
+ * upload them to the current device.
+ *   p in [1, 8] (order), n_cells_per_dim >= 1, half_width > 0 (bohr).
+ * The kinetic bound (fe_mesh_info) is Fried's element bound,
+ * lambda_max(K~/2) <= (1/2) lambda_max(W_e^{-1/2} K_e W_e^{-1/2}).
+ * Errors: FE_EINVAL (bad p, n, L or out == NULL), FE_ENOMEM, FE_EDEVICE. */
+fe_status fe_mesh_create(int p, int n_cells_per_dim, double half_width, fe_mesh* out);
+
+/* Sizes and the kinetic spectral bound; any output pointer may be NULL. */
+fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h,
+                       int* nodes_per_cell_h, double* kin_bound_h);
+
+/* Free-node coordinates xyz (N_f x 3, row-major, x fastest over nodes) and the
+ * lumped weights w (N_f). Either pointer may be NULL. */
+fe_status fe_mesh_nodes(fe_mesh mesh, double* xyz, double* w, void* stream);
+
+/* Diagonal of the kinetic part K~/2 at the free nodes (N_f doubles): the
+ * Jacobi preconditioner of the adjoint solve (Sec. 3.2.2). */
+fe_status fe_mesh_kinetic_diag(fe_mesh mesh, double* d, void* stream);
+
+fe_status fe_mesh_destroy(fe_mesh mesh);
+
+/* Bytes of device work buffer an operation needs for a block of nv columns
+ * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD). 0 on bad input. */
+size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec);
+
+const char* fe_last_error(void);
+
+/* ------------------------------------------------------------- ks_apply --
+ * Y = H~ X - X diag(shift):  Y = (1/2) W^{-1/2} K W^{-1/2} X + v .* X - shift_j X_j
+ * (Eqs. 17, 19; the matrix-free product of Sec. 3.2.3). The kinetic part is
+ * computed cell by cell and assembled without atomics, so the result is
+ * bitwise reproducible.
+ *   v: N_f doubles (always FP64). shift_h: nv host doubles or NULL (no shift),
+ *   at most 256 columns when given. X, Y: N_f x ld blocks of the precision's
+ *   type; Y must not alias X.
+ * prec: FE_F64, FE_F32 or FE_BF16. */
+fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const void* X, void* Y,
+                   int nv, int ld, fe_prec prec, void* stream);
+
+/* ---------------------------------------------------------- cheb_filter --
+ * X <- p_m(H~) X with the scaled degree-m Chebyshev filter of ChFSI
+ * (Sec. 3.2.2; Zhou and Saad 2007): with c = (a+b)/2, e = (b-a)/2,
+ *   p_m(lambda) = T_m((lambda - c)/e) / T_m((a0 - c)/e),
+ * which damps [a, b] and keeps the columns O(1) near a0 < a.
+ *   degree >= 1, a < b, a0 < a. work: fe_workspace_bytes(FE_OP_CHEB_FILTER).
+ * prec: FE_F64, FE_F32 or FE_BF16 (X's type follows prec). */
+fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, double b, double a0,
+                      void* X, int nv, int ld, fe_prec prec, void* work, void* stream);
+
+/* -------------------------------------------------------- rayleigh_ritz --
+ * Rayleigh-Ritz on span(X) (Eqs. 23-24), FP64: S = X^T X = L L^T,
+ * H_X = X^T H~ X, eigen-decomposition of L^{-1} H_X L^{-T} = V diag(eig) V^T,
+ * X <- X L^{-T} V (orthonormal Ritz vectors, ascending Ritz values in eig_h),
+ * resnorm_h[i] = || H~ x_i - eig_i x_i ||_2 (nullable).
+ * On FE_ENOTPD (S not positive definite) X is left unchanged.
+ * work: fe_workspace_bytes(FE_OP_RAYLEIGH_RITZ). Synchronises the stream. */
+fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h, double* resnorm_h,
+                        int nv, int ld, void* work, void* stream);
+
+/* ------------------------------------------------------- ks_eigensolve --
+ * Chebyshev-filtered subspace iteration (Sec. 3.2.2) for the nocc lowest
+ * eigenpairs: repeat { cheb_filter(degree) ; rayleigh_ritz } on the nv-column
+ * block X (nv > nocc; start from a random or warm block) until
+ * max_{i < nocc} ||H~ x_i - eig_i x_i|| <= tol or maxpass passes. The filter
+ * bounds are b = kinetic bound + max(v), a = largest Ritz value, a0 = smallest.
+ * prec selects the filter precision (FE_F64 / FE_F32 / FE_BF16); with a
+ * reduced precision the passes switch to FP64 once the residual is below
+ * `switch_tol`, so the final accuracy is FP64's. Rayleigh-Ritz is FP64.
+ *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.
+ *   passes_h: number of passes done (nullable).
+ * Returns FE_ENOCONV if maxpass was reached (X, eig_h, resnorm_h valid).
+ * work: fe_workspace_bytes(FE_OP_EIGENSOLVE, nv, prec). */
+fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld, int nocc,
+                        int degree, double tol, int maxpass, fe_prec prec, double switch_tol,
+                        double* eig_h, double* resnorm_h, int* passes_h, void* work, void* stream);
+
+/* --------------------------------------------------------- adjoint_solve --
+ * Solves, for all i < nocc together, (H~ - eps_i) q_i = b_i with Psi^T q_i = 0
+ * (Eq. 20, Sec. 3.2.2) by preconditioned MINRES (Paige and Saunders 1975),
+ * one Krylov space per column, all columns advanced in lockstep so that each
+ * iteration makes one ks_apply with per-column shifts. The operator and the
+ * preconditioner T = P diag(K~_aa/2)^{-1} P (P = I - Psi Psi^T, the inverse
+ * kinetic diagonal) are both restricted to the complement of the occupied
+ * orbitals. A column stops when its estimated relative residual is <= tol.
+ *   Psi: N_f x nocc orthonormal occupied orbitals (ld = nocc), eps_h: nocc
+ *   host doubles, B: right-hand sides (N_f x nocc, orthogonal to Psi), Q: out.
+ *   iters_h (nocc ints) and relres_h (nocc doubles: true ||b - A q|| / ||b||,
+ *   nullable) are filled on return.
+ * prec: FE_F64, or FE_F32 = FP32 inner MINRES with FP64 iterative refinement
+ * (residuals and updates of Q in FP64).
+ * Returns FE_ENOCONV when some column did not reach tol in maxit iterations.
+ * work: fe_workspace_bytes(FE_OP_ADJOINT_SOLVE, nocc, prec). Synchronises. */
+fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h,
+                        int nocc, const double* B, double* Q, double tol, int maxit, int* iters_h,
+                        double* relres_h, fe_prec prec, void* work, void* stream);
+
+/* ------------------------------------------------------------- loss_grad --
+ * Phase 1 (Q == NULL): rho_a = sum_i f_i psi_{a,i}^2 / W_a (Eq. 4),
+ *   loss = sum_a W_a (rho_data,a - rho_a)^2 (Eq. 1, w = 1), and the adjoint
+ *   right-hand sides B = -(I - Psi Psi^T) R with r_i = 4 f_i (rho - rho_data) psi_i
+ *   (Eqs. 7, 10, 20). Any of rho, B, loss_h may be NULL.
+ * Phase 2 (Q != NULL): grad_b = sum_i psi_{b,i} q_{b,i} (Eqs. 11, 22), then
+ *   grad_b = 0 where rho_data,b < tau_bc when tau_bc > 0 (Sec. 3.1.2).
+ *   Psi: N_f x nocc (ld = nocc); occ_h: nocc host doubles (f_i);
+ *   loss_h also returns the loss in phase 2 when rho is given.
+ * Synchronises the stream when loss_h != NULL. work: FE_OP_LOSS_GRAD bytes. */
+fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc,
+                    const double* rho_data, const double* Q, double tau_bc, double* rho, double* B,
+                    double* grad, double* loss_h, void* work, void* stream);
+
+/* --------------------------------------------------------- block helpers --
+ * Small FP64 vector kernels used by the host-side L-BFGS driver (Eq. 21):
+ * fe_dot returns sum_a x_a y_a over n entries (deterministic reduction);
+ * fe_axpby computes y <- alpha x + beta y. work: at least 64 KiB. */
+fe_status fe_dot(const double* x, const double* y, int64_t n, double* out_h, void* work, void* stream);
+fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INVDFT_H */

@@ -1,0 +1,196 @@
+"""Thin torch-facing binding of the C ABI (argument marshalling only).
+
+Tensors supply device memory; the current torch stream is passed to every call.
+Every computation runs in libinvdft.so; nothing here touches tensor values.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+PREC = {"f64": L.FE_F64, "f32": L.FE_F32, "bf16": L.FE_BF16}
+DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_doubles(vals):
+    if vals is None:
+        return None
+    arr = (C.c_double * len(vals))(*[float(x) for x in vals])
+    return arr
+
+
+def _work(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Mesh:
+    """Spectral-element mesh of [-L, L]^3 with n^3 cells of order p (device tables)."""
+
+    def __init__(self, p: int, n: int, half_width: float):
+        lib = L.load()
+        h = C.c_void_p()
+        L.check(lib.fe_mesh_create(int(p), int(n), float(half_width), C.byref(h)), "fe_mesh_create")
+        self._h = h
+        self.p, self.n, self.half_width = int(p), int(n), float(half_width)
+        nf, nc, npc, kb = C.c_int64(), C.c_int64(), C.c_int(), C.c_double()
+        L.check(lib.fe_mesh_info(h, C.byref(nf), C.byref(nc), C.byref(npc), C.byref(kb)), "fe_mesh_info")
+        self.n_free, self.n_cells, self.nodes_per_cell, self.kin_bound = nf.value, nc.value, npc.value, kb.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            L.load().fe_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self):
+        xyz = torch.empty((self.n_free, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty(self.n_free, dtype=torch.float64, device=self.device)
+        L.check(L.load().fe_mesh_nodes(self._h, _ptr(xyz), _ptr(w), _stream()), "fe_mesh_nodes")
+        return xyz, w
+
+    def kinetic_diag(self):
+        d = torch.empty(self.n_free, dtype=torch.float64, device=self.device)
+        L.check(L.load().fe_mesh_kinetic_diag(self._h, _ptr(d), _stream()), "fe_mesh_kinetic_diag")
+        return d
+
+    def workspace_bytes(self, op: int, nv: int, prec: str = "f64") -> int:
+        return int(L.load().fe_workspace_bytes(self._h, op, nv, PREC[prec]))
+
+
+def ks_apply(mesh: Mesh, v, X, Y=None, shift=None, prec: str = "f64"):
+    """Y = H~ X - X diag(shift) (one call of the C ABI)."""
+    nv = X.shape[1]
+    if Y is None:
+        Y = torch.empty_like(X)
+    sh = _host_doubles(shift)
+    L.check(L.load().ks_apply(mesh.handle, _ptr(v), sh, _ptr(X), _ptr(Y), nv, nv, PREC[prec], _stream()),
+            "ks_apply")
+    return Y
+
+
+def cheb_filter(mesh: Mesh, v, degree: int, a: float, b: float, a0: float, X, prec: str = "f64", work=None):
+    nv = X.shape[1]
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_CHEB_FILTER, nv, prec), X.device)
+    L.check(L.load().cheb_filter(mesh.handle, _ptr(v), int(degree), float(a), float(b), float(a0), _ptr(X), nv, nv,
+                                 PREC[prec], _ptr(work), _stream()), "cheb_filter")
+    return X
+
+
+def rayleigh_ritz(mesh: Mesh, v, X, work=None):
+    nv = X.shape[1]
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_RAYLEIGH_RITZ, nv), X.device)
+    eig = (C.c_double * nv)()
+    res = (C.c_double * nv)()
+    L.check(L.load().rayleigh_ritz(mesh.handle, _ptr(v), _ptr(X), eig, res, nv, nv, _ptr(work), _stream()),
+            "rayleigh_ritz")
+    return list(eig), list(res)
+
+
+@dataclass
+class EigResult:
+    eig: list
+    res: list
+    passes: int
+    status: int
+
+
+def ks_eigensolve(mesh: Mesh, v, X, nocc: int, degree: int, tol: float, maxpass: int, prec: str = "f64",
+                  switch_tol: float = 1e-5, work=None, allow=(L.FE_ENOCONV, L.FE_EGAP)) -> EigResult:
+    nv = X.shape[1]
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, nv, prec), X.device)
+    eig = (C.c_double * nv)()
+    res = (C.c_double * nv)()
+    passes = C.c_int()
+    st = L.load().ks_eigensolve(mesh.handle, _ptr(v), _ptr(X), nv, nv, int(nocc), int(degree), float(tol),
+                                int(maxpass), PREC[prec], float(switch_tol), eig, res, C.byref(passes), _ptr(work),
+                                _stream())
+    L.check(st, "ks_eigensolve", allow=allow)
+    return EigResult(list(eig), list(res), passes.value, st)
+
+
+@dataclass
+class AdjResult:
+    iters: list
+    relres: list
+    status: int
+
+
+def adjoint_solve(mesh: Mesh, v, Psi, eps, B, Q=None, tol: float = 1e-10, maxit: int = 5000, prec: str = "f64",
+                  work=None, allow=(L.FE_ENOCONV,)) -> tuple:
+    k = Psi.shape[1]
+    if Q is None:
+        Q = torch.empty_like(B)
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, k, prec), Psi.device)
+    its = (C.c_int * k)()
+    rel = (C.c_double * k)()
+    st = L.load().adjoint_solve(mesh.handle, _ptr(v), _ptr(Psi), _host_doubles(eps), k, _ptr(B), _ptr(Q),
+                                float(tol), int(maxit), its, rel, PREC[prec], _ptr(work), _stream())
+    L.check(st, "adjoint_solve", allow=allow)
+    return Q, AdjResult(list(its), list(rel), st)
+
+
+def loss_grad(mesh: Mesh, Psi, occ, rho_data, Q=None, tau_bc: float = 0.0, want_rho=True, want_B=True,
+              work=None):
+    """Phase 1 (Q is None): returns (rho, B, loss). Phase 2: returns grad."""
+    k = Psi.shape[1]
+    dev = Psi.device
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_LOSS_GRAD, k), dev)
+    lib = L.load()
+    occ_h = _host_doubles(occ)
+    if Q is None:
+        rho = torch.empty(mesh.n_free, dtype=torch.float64, device=dev) if want_rho else None
+        B = torch.empty_like(Psi) if want_B else None
+        loss = C.c_double()
+        L.check(lib.loss_grad(mesh.handle, _ptr(Psi), occ_h, k, _ptr(rho_data), None, 0.0, _ptr(rho), _ptr(B), None,
+                              C.byref(loss), _ptr(work), _stream()), "loss_grad")
+        return rho, B, loss.value
+    g = torch.empty(mesh.n_free, dtype=torch.float64, device=dev)
+    L.check(lib.loss_grad(mesh.handle, _ptr(Psi), occ_h, k, _ptr(rho_data), _ptr(Q), float(tau_bc), None, None,
+                          _ptr(g), None, _ptr(work), _stream()), "loss_grad")
+    return g
+
+
+def dot(x, y, work=None) -> float:
+    if work is None:
+        work = _work(65536, x.device)
+    out = C.c_double()
+    L.check(L.load().fe_dot(_ptr(x), _ptr(y), x.numel(), C.byref(out), _ptr(work), _stream()), "fe_dot")
+    return out.value
+
+
+def axpby(alpha: float, x, beta: float, y):
+    L.check(L.load().fe_axpby(float(alpha), _ptr(x), float(beta), _ptr(y), x.numel(), _stream()), "fe_axpby")
+    return y

@@ -1,0 +1,676 @@
+// C ABI of the inverse-DFT hot path: argument checks, work-buffer layout and
+// the host-side control of the iterative methods. All arithmetic on blocks
+// runs in the HIP kernels of apply.hip, blockops.hip and krylov.hip; the host
+// only does O(nv^3) dense FP64 algebra on nv x nv projected matrices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "krylov.h"
+
+struct fe_mesh_s {
+  invdft::Mesh m;
+};
+
+namespace invdft {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+fe_status fail(fe_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+fe_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+  return FE_EDEVICE;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's work buffer; with base == nullptr it only measures.
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+fe_status check_mesh(fe_mesh mesh) {
+  if (!mesh) return fail(FE_EINVAL, "mesh handle is NULL");
+  return FE_OK;
+}
+
+fe_status check_block(const void* X, const char* name, int nv, int ld) {
+  if (!X) return fail(FE_EINVAL, std::string(name) + " is NULL");
+  if (!aligned16(X)) return fail(FE_EINVAL, std::string(name) + " is not 16-byte aligned");
+  if (nv < 1) return fail(FE_EINVAL, "nv must be >= 1");
+  if (ld < nv) return fail(FE_EINVAL, "ld must be >= nv");
+  return FE_OK;
+}
+
+size_t elem_size(fe_prec p) { return p == FE_F64 ? sizeof(double) : sizeof(float); }
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- filter
+// Scaled three-term recurrence of the Chebyshev filter (Zhou and Saad 2007):
+// Y1 = (sigma1/e)(H - c)X, Y_{k+1} = (2 sigma_{k+1}/e)(H - c)Y_k - sigma_k sigma_{k+1} Y_{k-1},
+// sigma_{k+1} = 1 / (2/sigma1 - sigma_k). Two blocks suffice: the newest block
+// overwrites the oldest one, which the kernel reads element by element before it writes.
+fe_status filter_impl(const Mesh& m, const double* v, int degree, double a, double b, double a0, void* X, int nv,
+                      int ld, fe_prec prec, void* work, hipStream_t s) {
+  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+  const double sigma1 = e / (a0 - c);
+  double sigma = sigma1;
+  const double gamma = 2.0 / sigma1;
+  void* bufs[2] = {X, work};
+  ApplyArgs aa{};
+  aa.v = v;
+  aa.nv = nv;
+  aa.ld = ld;
+  aa.cshift = c;
+  // step 1: work = (sigma1/e)(H - c) X
+  aa.X = X;
+  aa.Y = work;
+  aa.Z = nullptr;
+  aa.alpha = sigma1 / e;
+  aa.beta = 0.0;
+  fe_status st = launch_apply(m, aa, prec, s);
+  if (st != FE_OK) return st;
+  int cur = 1;  // bufs[cur] holds Y_k, bufs[1-cur] holds Y_{k-1}
+  for (int k = 2; k <= degree; ++k) {
+    const double sigma_new = 1.0 / (gamma - sigma);
+    aa.X = bufs[cur];
+    aa.Z = bufs[1 - cur];
+    aa.Y = bufs[1 - cur];
+    aa.alpha = 2.0 * sigma_new / e;
+    aa.beta = -sigma * sigma_new;
+    st = launch_apply(m, aa, prec, s);
+    if (st != FE_OK) return st;
+    sigma = sigma_new;
+    cur = 1 - cur;
+  }
+  if (cur == 1) INVDFT_HIP(hipMemcpyAsync(X, work, (size_t)m.nf * ld * elem_size(prec), hipMemcpyDeviceToDevice, s));
+  return FE_OK;
+}
+
+size_t filter_work(const Mesh& m, int ld, fe_prec prec) { return align_up((size_t)m.nf * ld * elem_size(prec)); }
+
+// ------------------------------------------------------------ Rayleigh-Ritz
+struct RRWork {
+  double *HX, *S, *H, *C, *lam, *res, *gw;
+};
+
+RRWork rr_layout(Bump& bp, const Mesh& m, int nv, int ld) {
+  RRWork w{};
+  w.HX = bp.take<double>((size_t)m.nf * ld);
+  w.S = bp.take<double>((size_t)nv * nv);
+  w.H = bp.take<double>((size_t)nv * nv);
+  w.C = bp.take<double>((size_t)nv * nv);
+  w.lam = bp.take<double>(nv);
+  w.res = bp.take<double>(nv);
+  w.gw = bp.take<double>(std::max(gram_work_bytes(m.nf, nv, nv), coldot_work_bytes(m.nf, nv)) / sizeof(double) + 1);
+  return w;
+}
+
+fe_status rr_impl(const Mesh& m, const double* v, double* X, double* eig_h, double* res_h, int nv, int ld,
+                  void* work, hipStream_t s) {
+  if (nv > 64) return fail(FE_EINVAL, "rayleigh_ritz: at most 64 columns are supported");
+  Bump bp(work);
+  RRWork w = rr_layout(bp, m, nv, ld);
+  fe_status st = gram(X, ld, X, ld, m.nf, nv, nv, false, w.S, w.gw, s);
+  if (st != FE_OK) return st;
+  ApplyArgs aa{};
+  aa.X = X;
+  aa.Y = w.HX;
+  aa.v = v;
+  aa.nv = nv;
+  aa.ld = ld;
+  aa.alpha = 1.0;
+  st = launch_apply(m, aa, FE_F64, s);
+  if (st != FE_OK) return st;
+  st = gram(X, ld, w.HX, ld, m.nf, nv, nv, false, w.H, w.gw, s);
+  if (st != FE_OK) return st;
+  std::vector<double> Sh((size_t)nv * nv), Hh((size_t)nv * nv);
+  INVDFT_HIP(hipMemcpyAsync(Sh.data(), w.S, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(Hh.data(), w.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  for (double x : Sh)
+    if (!std::isfinite(x)) return fail(FE_ENOTPD, "rayleigh_ritz: overlap matrix is not finite");
+  // S = L L^T ; A = L^{-1} H L^{-T} ; A = V diag(lam) V^T ; C = L^{-T} V  (Eq. 24)
+  if (!cholesky_lower(nv, Sh.data())) return fail(FE_ENOTPD, "rayleigh_ritz: overlap matrix is not positive definite");
+  std::vector<double> Li((size_t)nv * nv), T((size_t)nv * nv, 0.0), A((size_t)nv * nv, 0.0);
+  invert_lower(nv, Sh.data(), Li.data());
+  for (int i = 0; i < nv; ++i)  // symmetrise H_X
+    for (int j = 0; j < i; ++j) {
+      const double a = 0.5 * (Hh[(size_t)i * nv + j] + Hh[(size_t)j * nv + i]);
+      Hh[(size_t)i * nv + j] = Hh[(size_t)j * nv + i] = a;
+    }
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) {
+      double t = 0.0;
+      for (int k = 0; k <= i; ++k) t += Li[(size_t)i * nv + k] * Hh[(size_t)k * nv + j];
+      T[(size_t)i * nv + j] = t;
+    }
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double t = 0.0;
+      for (int k = 0; k <= j; ++k) t += T[(size_t)i * nv + k] * Li[(size_t)j * nv + k];
+      A[(size_t)i * nv + j] = A[(size_t)j * nv + i] = t;
+    }
+  std::vector<double> lam(nv), V((size_t)nv * nv), C((size_t)nv * nv, 0.0);
+  jacobi_eigh(nv, A.data(), lam.data(), V.data());
+  for (int i = 0; i < nv; ++i)  // C = L^{-T} V: (L^{-T})_{ik} = Li[k][i], nonzero for k >= i
+    for (int j = 0; j < nv; ++j) {
+      double t = 0.0;
+      for (int k = i; k < nv; ++k) t += Li[(size_t)k * nv + i] * V[(size_t)k * nv + j];
+      C[(size_t)i * nv + j] = t;
+    }
+  INVDFT_HIP(hipMemcpyAsync(w.C, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  INVDFT_HIP(hipMemcpyAsync(w.lam, lam.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
+  st = rotate(X, ld, m.nf, nv, w.C, nv, X, ld, s);
+  if (st != FE_OK) return st;
+  st = rotate(w.HX, ld, m.nf, nv, w.C, nv, w.HX, ld, s);
+  if (st != FE_OK) return st;
+  std::vector<double> res(nv);
+  st = colresid(w.HX, X, w.lam, ld, m.nf, nv, w.res, w.gw, s);
+  if (st != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(res.data(), w.res, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < nv; ++i) {
+    if (eig_h) eig_h[i] = lam[i];
+    if (res_h) res_h[i] = std::sqrt(std::max(res[i], 0.0));
+  }
+  return FE_OK;
+}
+
+// -------------------------------------------------------------- eigensolve
+struct EigWork {
+  void* rr;
+  void* filt;   // filter work block (precision of the filter)
+  float* Xf;    // FP32 copy of X for the reduced-precision filter
+  double* vmax;
+  void* redw;
+};
+
+EigWork eig_layout(Bump& bp, const Mesh& m, int nv, int ld, fe_prec prec) {
+  EigWork w{};
+  Bump rrb(nullptr);
+  rr_layout(rrb, m, nv, ld);
+  w.rr = bp.take<char>(rrb.off);
+  w.filt = bp.take<char>(filter_work(m, ld, FE_F64));  // large enough for either filter precision
+  w.Xf = prec == FE_F64 ? nullptr : bp.take<float>((size_t)m.nf * ld);
+  w.vmax = bp.take<double>(1);
+  w.redw = bp.take<double>(1025);
+  return w;
+}
+
+// ------------------------------------------------------------------ MINRES
+struct MRWork {
+  double *R1, *R2, *Z, *Y, *Wa, *Wb, *dinv, *st, *d1, *d2, *bnorm, *dots, *pw, *qcopy;
+};
+
+MRWork mr_layout(Bump& bp, const Mesh& m, int k) {
+  MRWork w{};
+  const size_t blk = (size_t)m.nf * k;
+  w.R1 = bp.take<double>(blk);
+  w.R2 = bp.take<double>(blk);
+  w.Z = bp.take<double>(blk);
+  w.Y = bp.take<double>(blk);
+  w.Wa = bp.take<double>(blk);
+  w.Wb = bp.take<double>(blk);
+  w.dinv = bp.take<double>(m.nf);
+  w.st = bp.take<double>((size_t)mr_state_count() * k);
+  w.d1 = bp.take<double>(k);
+  w.d2 = bp.take<double>(k);
+  w.bnorm = bp.take<double>(k);
+  w.dots = bp.take<double>(mr_dots_work_bytes(m.nf, k) / sizeof(double) + 1);
+  w.pw = bp.take<double>(std::max(project_work_bytes(m.nf, k, k), coldot_work_bytes(m.nf, k)) / sizeof(double) + 1);
+  return w;
+}
+
+// One FP64 MINRES solve of P (H - eps_i) P q_i = b_i, q_i in the complement of Psi.
+fe_status minres_f64(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k, const double* B,
+                     double* Q, double tol, int maxit, MRWork& w, int* iters_h, double* relres_h, bool* converged,
+                     hipStream_t s) {
+  const int64_t nf = m.nf;
+  const size_t blk = (size_t)nf * k;
+  fe_status st;
+  if ((st = fill(Q, 0.0, blk, s)) != FE_OK) return st;
+  if ((st = fill(w.Wa, 0.0, blk, s)) != FE_OK) return st;
+  if ((st = fill(w.Wb, 0.0, blk, s)) != FE_OK) return st;
+  if ((st = copy_block(B, w.R1, blk, s)) != FE_OK) return st;
+  if ((st = copy_block(B, w.R2, blk, s)) != FE_OK) return st;
+  if ((st = k_dinv(m, w.dinv, s)) != FE_OK) return st;
+  // z = P D^{-1} b ; beta1 = sqrt(b.z)
+  if ((st = k_precond(B, w.dinv, k, nf, w.Z, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, k, w.Z, k, nf, false, w.pw, s)) != FE_OK) return st;
+  if ((st = coldot(w.R1, w.Z, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = mr_init(w.st, w.d1, k, s)) != FE_OK) return st;
+  double *R1 = w.R1, *R2 = w.R2, *Z = w.Z, *Y = w.Y, *Wa = w.Wa, *Wb = w.Wb;
+  ApplyArgs aa{};
+  aa.v = v;
+  aa.nv = k;
+  aa.ld = k;
+  aa.alpha = 1.0;
+  aa.colshift = eps_h;
+  std::vector<double> active(k);
+  int it = 0;
+  bool all_done = false;
+  const int check_every = 8;
+  for (it = 1; it <= maxit; ++it) {
+    // y = P (H - eps) (z / beta)
+    aa.X = Z;
+    aa.Y = Y;
+    aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
+    if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
+    // alfa = v.(y - c1 r1)
+    if ((st = mr_dots(Z, Y, R1, k, nf, w.d1, w.d2, w.dots, s)) != FE_OK) return st;
+    if ((st = mr_alfa(w.st, w.d1, w.d2, k, it == 1, s)) != FE_OK) return st;
+    // r_new = y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; u <- P u
+    if ((st = mr_resid_precond(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
+    std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
+    if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
+    if ((st = coldot(R2, Y, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
+    if ((st = mr_givens(w.st, w.d1, k, tol, s)) != FE_OK) return st;
+    if ((st = mr_update(Z, Wb, Wa, Q, w.st, k, nf, s)) != FE_OK) return st;
+    std::swap(Wa, Wb);
+    std::swap(Z, Y);
+    if (it % check_every == 0 || it == maxit) {
+      INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+      INVDFT_HIP(hipStreamSynchronize(s));
+      all_done = true;
+      for (int j = 0; j < k; ++j)
+        if (active[j] > 0.0) all_done = false;
+      if (all_done) break;
+    }
+  }
+  // final projection (round-off only) and the true residual ||b - P(H - eps)q|| / ||b||
+  if ((st = project_out(Psi, k, Q, k, nf, false, w.pw, s)) != FE_OK) return st;
+  aa.X = Q;
+  aa.Y = Y;
+  aa.d_colscale = nullptr;
+  if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
+  if ((st = k_sub_from(B, Y, blk, s)) != FE_OK) return st;
+  if ((st = coldot(Y, Y, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = coldot(B, B, k, nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
+  std::vector<double> rr(k), bb(k), its(k);
+  INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(its.data(), w.st + (size_t)mr_state_iters() * k, k * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    if (iters_h) iters_h[j] = (int)its[j];
+    if (relres_h) relres_h[j] = bb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / bb[j]) : 0.0;
+    if (active[j] > 0.0) ok = false;
+  }
+  *converged = ok;
+  return FE_OK;
+}
+
+}  // namespace
+}  // namespace invdft
+
+using namespace invdft;
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* fe_last_error(void) { return g_err.c_str(); }
+
+fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
+  if (!out) return fail(FE_EINVAL, "fe_mesh_create: out is NULL");
+  *out = nullptr;
+  if (p < 1 || p > kMaxP) return fail(FE_EINVAL, "fe_mesh_create: p must be in [1, 8]");
+  if (n < 1) return fail(FE_EINVAL, "fe_mesh_create: n must be >= 1");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(FE_EINVAL, "fe_mesh_create: half_width must be > 0");
+  const long long n1 = (long long)p * n - 1;
+  if (n1 > 2000) return fail(FE_EINVAL, "fe_mesh_create: mesh too large");
+  auto* h = new (std::nothrow) fe_mesh_s();
+  if (!h) return fail(FE_ENOMEM, "fe_mesh_create: host allocation failed");
+  Mesh& m = h->m;
+  m.p = p;
+  m.n = n;
+  m.n1 = (int)n1;
+  m.L = L;
+  m.h = 2.0 * L / n;
+  m.nf = n1 * n1 * n1;
+  const int P1 = p + 1;
+  std::vector<double> Kh(P1 * P1), Mh(P1 * P1), xi(P1), wi(P1);
+  reference_matrices(p, Kh.data(), Mh.data(), xi.data(), wi.data());
+  // assembled 1-D GLL weights at the element's local nodes: vertices are shared by two cells
+  std::vector<double> wloc(P1), sloc(P1);
+  for (int i = 0; i < P1; ++i) {
+    wloc[i] = (i == 0 || i == p) ? m.h * wi[0] : 0.5 * m.h * wi[i];
+    sloc[i] = 1.0 / std::sqrt(wloc[i]);
+  }
+  for (int i = 0; i < P1; ++i)
+    for (int k = 0; k < P1; ++k) {
+      m.mt[i * P1 + k] = sloc[i] * (0.5 * m.h) * Mh[i * P1 + k] * sloc[k];
+      m.kt[i * P1 + k] = sloc[i] * (2.0 / m.h) * Kh[i * P1 + k] * sloc[k];
+    }
+  // exact symmetry and centrosymmetry (the kernels read one canonical copy of each entry)
+  for (double* A : {m.mt, m.kt}) {
+    double B[kMaxP1 * kMaxP1];
+    for (int i = 0; i < P1; ++i)
+      for (int k = 0; k < P1; ++k)
+        B[i * P1 + k] = 0.25 * (A[i * P1 + k] + A[k * P1 + i] + A[(p - i) * P1 + (p - k)] + A[(p - k) * P1 + (p - i)]);
+    std::memcpy(A, B, sizeof(double) * P1 * P1);
+  }
+  m.x1.resize(n1);
+  m.w1.resize(n1);
+  m.kd1.resize(n1);
+  m.md1.resize(n1);
+  for (long long f = 0; f < n1; ++f) {
+    const long long g = f + 1;
+    const long long e = g / p;
+    const int j = (int)(g % p);
+    m.x1[f] = -L + m.h * (e + 0.5 * (xi[j] + 1.0));
+    m.w1[f] = wloc[j];
+    m.kd1[f] = (j == 0) ? m.kt[p * P1 + p] + m.kt[0] : m.kt[j * P1 + j];
+    m.md1[f] = (j == 0) ? m.mt[p * P1 + p] + m.mt[0] : m.mt[j * P1 + j];
+  }
+  // Fried element bound: (1/2) lambda_max(W_e^{-1/2} K_e W_e^{-1/2}), W_e the element's own lumped mass
+  {
+    const int np = P1 * P1 * P1;
+    std::vector<double> A((size_t)np * np);
+    std::vector<double> ke(P1 * P1), me(P1 * P1), we(P1);
+    for (int i = 0; i < P1 * P1; ++i) {
+      ke[i] = (2.0 / m.h) * Kh[i];
+      me[i] = (0.5 * m.h) * Mh[i];
+    }
+    for (int i = 0; i < P1; ++i) we[i] = 0.5 * m.h * wi[i];
+    for (int a = 0; a < np; ++a) {
+      const int ai = a % P1, aj = (a / P1) % P1, ak = a / (P1 * P1);
+      for (int b = 0; b < np; ++b) {
+        const int bi = b % P1, bj = (b / P1) % P1, bk = b / (P1 * P1);
+        const double kk = ke[ai * P1 + bi] * me[aj * P1 + bj] * me[ak * P1 + bk] +
+                          me[ai * P1 + bi] * ke[aj * P1 + bj] * me[ak * P1 + bk] +
+                          me[ai * P1 + bi] * me[aj * P1 + bj] * ke[ak * P1 + bk];
+        const double wa = we[ai] * we[aj] * we[ak], wb = we[bi] * we[bj] * we[bk];
+        A[(size_t)a * np + b] = kk / std::sqrt(wa * wb);
+      }
+    }
+    double lmax;
+    if (p <= 5) {
+      lmax = max_eig_sym(np, A.data());
+    } else {  // Gershgorin: rigorous, looser
+      lmax = 0.0;
+      for (int a = 0; a < np; ++a) {
+        double r = 0.0;
+        for (int b = 0; b < np; ++b) r += std::fabs(A[(size_t)a * np + b]);
+        lmax = std::max(lmax, r);
+      }
+    }
+    m.kin_bound = 0.5 * lmax;
+  }
+  hipError_t e = hipGetDevice(&m.device);
+  if (e == hipSuccess) e = hipMalloc(&m.d_x1, n1 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&m.d_w1, n1 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&m.d_kd1, n1 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&m.d_md1, n1 * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(m.d_x1, m.x1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m.d_w1, m.w1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m.d_kd1, m.kd1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m.d_md1, m.md1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fe_mesh_destroy(h);
+    return e == hipErrorOutOfMemory ? fail(FE_ENOMEM, "fe_mesh_create: device allocation failed")
+                                    : hip_fail(e, "fe_mesh_create");
+  }
+  *out = h;
+  return FE_OK;
+}
+
+fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h, int* nodes_per_cell_h,
+                       double* kin_bound_h) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  const Mesh& m = mesh->m;
+  if (n_free_h) *n_free_h = m.nf;
+  if (n_cells_h) *n_cells_h = (int64_t)m.n * m.n * m.n;
+  if (nodes_per_cell_h) *nodes_per_cell_h = (m.p + 1) * (m.p + 1) * (m.p + 1);
+  if (kin_bound_h) *kin_bound_h = m.kin_bound;
+  return FE_OK;
+}
+
+fe_status fe_mesh_nodes(fe_mesh mesh, double* xyz, double* w, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  if (!xyz && !w) return FE_OK;
+  return k_nodes(mesh->m, xyz, w, S(stream));
+}
+
+fe_status fe_mesh_kinetic_diag(fe_mesh mesh, double* d, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  if (!d) return fail(FE_EINVAL, "fe_mesh_kinetic_diag: d is NULL");
+  return k_kdiag(mesh->m, d, S(stream));
+}
+
+fe_status fe_mesh_destroy(fe_mesh mesh) {
+  if (!mesh) return FE_OK;
+  Mesh& m = mesh->m;
+  if (m.d_x1) (void)hipFree(m.d_x1);
+  if (m.d_w1) (void)hipFree(m.d_w1);
+  if (m.d_kd1) (void)hipFree(m.d_kd1);
+  if (m.d_md1) (void)hipFree(m.d_md1);
+  delete mesh;
+  return FE_OK;
+}
+
+size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
+  if (!mesh || nv < 1) return 0;
+  const Mesh& m = mesh->m;
+  Bump bp(nullptr);
+  switch (op) {
+    case FE_OP_KS_APPLY: return 0;
+    case FE_OP_CHEB_FILTER: return filter_work(m, nv, prec);
+    case FE_OP_RAYLEIGH_RITZ: rr_layout(bp, m, nv, nv); return bp.off;
+    case FE_OP_EIGENSOLVE: eig_layout(bp, m, nv, nv, prec); return bp.off;
+    case FE_OP_ADJOINT_SOLVE: mr_layout(bp, m, nv); return bp.off;
+    case FE_OP_LOSS_GRAD:
+      bp.take<double>(m.nf);
+      bp.take<double>(1025);
+      bp.take<double>(project_work_bytes(m.nf, nv, nv) / sizeof(double) + 1);
+      return bp.off;
+    default: return 0;
+  }
+}
+
+fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const void* X, void* Y, int nv, int ld,
+                   fe_prec prec, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  fe_status st;
+  if ((st = check_block(X, "X", nv, ld)) != FE_OK) return st;
+  if ((st = check_block(Y, "Y", nv, ld)) != FE_OK) return st;
+  if (!v) return fail(FE_EINVAL, "ks_apply: v is NULL");
+  if (X == Y) return fail(FE_EINVAL, "ks_apply: Y must not alias X");
+  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "ks_apply: unsupported precision");
+  ApplyArgs aa{};
+  aa.X = X;
+  aa.Y = Y;
+  aa.v = v;
+  aa.nv = nv;
+  aa.ld = ld;
+  aa.alpha = 1.0;
+  aa.colshift = shift_h;
+  return launch_apply(mesh->m, aa, prec, S(stream));
+}
+
+fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, double b, double a0, void* X, int nv,
+                      int ld, fe_prec prec, void* work, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  fe_status st;
+  if ((st = check_block(X, "X", nv, ld)) != FE_OK) return st;
+  if (!v) return fail(FE_EINVAL, "cheb_filter: v is NULL");
+  if (!work) return fail(FE_EINVAL, "cheb_filter: work is NULL");
+  if (degree < 1) return fail(FE_EINVAL, "cheb_filter: degree must be >= 1");
+  if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "cheb_filter: need a0 < a < b");
+  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "cheb_filter: unsupported precision");
+  return filter_impl(mesh->m, v, degree, a, b, a0, X, nv, ld, prec, work, S(stream));
+}
+
+fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h, double* resnorm_h, int nv, int ld,
+                        void* work, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  fe_status st;
+  if ((st = check_block(X, "X", nv, ld)) != FE_OK) return st;
+  if (!v || !work || !eig_h) return fail(FE_EINVAL, "rayleigh_ritz: v, work and eig_h are required");
+  return rr_impl(mesh->m, v, X, eig_h, resnorm_h, nv, ld, work, S(stream));
+}
+
+fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld, int nocc, int degree, double tol,
+                        int maxpass, fe_prec prec, double switch_tol, double* eig_h, double* resnorm_h,
+                        int* passes_h, void* work, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  fe_status st;
+  if ((st = check_block(X, "X", nv, ld)) != FE_OK) return st;
+  if (!v || !work || !eig_h || !resnorm_h) return fail(FE_EINVAL, "ks_eigensolve: v, work, eig_h, resnorm_h required");
+  if (nocc < 1 || nocc >= nv) return fail(FE_EINVAL, "ks_eigensolve: need 1 <= nocc < nv");
+  if (degree < 1 || maxpass < 0) return fail(FE_EINVAL, "ks_eigensolve: degree >= 1 and maxpass >= 0 required");
+  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "ks_eigensolve: unsupported precision");
+  const Mesh& m = mesh->m;
+  hipStream_t s = S(stream);
+  Bump bp(work);
+  EigWork w = eig_layout(bp, m, nv, ld, prec);
+  if ((st = max1(v, m.nf, w.vmax, w.redw, s)) != FE_OK) return st;
+  double vmax = 0.0;
+  INVDFT_HIP(hipMemcpyAsync(&vmax, w.vmax, sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  const double b = m.kin_bound + vmax;
+  if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
+  int pass = 0;
+  bool conv = false;
+  for (;;) {
+    double rmax = 0.0;
+    for (int i = 0; i < nocc; ++i) rmax = std::max(rmax, resnorm_h[i]);
+    if (rmax <= tol) {
+      conv = true;
+      break;
+    }
+    if (pass >= maxpass) break;
+    const double a = eig_h[nv - 1], a0 = eig_h[0];
+    if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "ks_eigensolve: degenerate filter interval");
+    if (prec != FE_F64 && rmax > switch_tol) {
+      if ((st = cast_block_to_f32(X, w.Xf, (int64_t)m.nf * ld, s)) != FE_OK) return st;
+      if ((st = filter_impl(m, v, degree, a, b, a0, w.Xf, nv, ld, FE_F32, w.filt, s)) != FE_OK) return st;
+      if ((st = cast_block_to_f64(w.Xf, X, (int64_t)m.nf * ld, s)) != FE_OK) return st;
+    } else {
+      if ((st = filter_impl(m, v, degree, a, b, a0, X, nv, ld, FE_F64, w.filt, s)) != FE_OK) return st;
+    }
+    if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
+    ++pass;
+  }
+  if (passes_h) *passes_h = pass;
+  if (!conv) return fail(FE_ENOCONV, "ks_eigensolve: residual tolerance not reached in maxpass passes");
+  if (eig_h[nocc] - eig_h[nocc - 1] < 1e-6) return fail(FE_EGAP, "ks_eigensolve: no gap at the Fermi level");
+  return FE_OK;
+}
+
+fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc, const double* rho_data,
+                    const double* Q, double tau_bc, double* rho, double* B, double* grad, double* loss_h, void* work,
+                    void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  if (!Psi || !occ_h) return fail(FE_EINVAL, "loss_grad: Psi and occ_h are required");
+  if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "loss_grad: nocc must be in [1, 64]");
+  const Mesh& m = mesh->m;
+  hipStream_t s = S(stream);
+  fe_status st;
+  if (Q) {
+    if (!grad) return fail(FE_EINVAL, "loss_grad: phase 2 needs grad");
+    if (tau_bc > 0 && !rho_data) return fail(FE_EINVAL, "loss_grad: tau_bc needs rho_data");
+    if ((st = k_grad(m, Psi, Q, nocc, rho_data, tau_bc, grad, s)) != FE_OK) return st;
+    if (loss_h && rho && rho_data) {
+      if (!work) return fail(FE_EINVAL, "loss_grad: work is NULL");
+      Bump bp(work);
+      bp.take<double>(m.nf);
+      double* lw = bp.take<double>(1025);
+      double* dl = lw + 1024;
+      if ((st = k_loss(m, rho, rho_data, dl, lw, s)) != FE_OK) return st;
+      INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+      INVDFT_HIP(hipStreamSynchronize(s));
+    }
+    return FE_OK;
+  }
+  if (!work) return fail(FE_EINVAL, "loss_grad: work is NULL");
+  if ((B || loss_h) && !rho_data) return fail(FE_EINVAL, "loss_grad: rho_data is required for the loss and B");
+  Bump bp(work);
+  double* rho_w = bp.take<double>(m.nf);
+  double* lw = bp.take<double>(1025);
+  void* pw = bp.take<char>(project_work_bytes(m.nf, nocc, nocc));
+  double* r = rho ? rho : rho_w;
+  if ((st = k_density(m, Psi, nocc, occ_h, r, s)) != FE_OK) return st;
+  if (B) {
+    if ((st = k_rhs(m, Psi, nocc, occ_h, r, rho_data, B, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, nocc, B, nocc, m.nf, false, pw, s)) != FE_OK) return st;
+  }
+  if (loss_h) {
+    double* dl = lw + 1024;
+    if ((st = k_loss(m, r, rho_data, dl, lw, s)) != FE_OK) return st;
+    INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+    INVDFT_HIP(hipStreamSynchronize(s));
+  }
+  return FE_OK;
+}
+
+fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h, int nocc,
+                        const double* B, double* Q, double tol, int maxit, int* iters_h, double* relres_h, fe_prec prec,
+                        void* work, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  if (!v || !Psi || !eps_h || !B || !Q || !work) return fail(FE_EINVAL, "adjoint_solve: NULL argument");
+  if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "adjoint_solve: nocc must be in [1, 64]");
+  if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve: tol > 0 and maxit >= 1 required");
+  if (prec != FE_F64) return fail(FE_EINVAL, "adjoint_solve: unsupported precision");
+  const Mesh& m = mesh->m;
+  hipStream_t s = S(stream);
+  Bump bp(work);
+  MRWork w = mr_layout(bp, m, nocc);
+  bool conv = false;
+  fe_status st = minres_f64(m, v, Psi, eps_h, nocc, B, Q, tol, maxit, w, iters_h, relres_h, &conv, s);
+  if (st != FE_OK) return st;
+  if (!conv) return fail(FE_ENOCONV, "adjoint_solve: some columns did not converge in maxit iterations");
+  return FE_OK;
+}
+
+fe_status fe_dot(const double* x, const double* y, int64_t n, double* out_h, void* work, void* stream) {
+  if (!x || !y || !out_h || !work || n < 0) return fail(FE_EINVAL, "fe_dot: bad argument");
+  hipStream_t s = S(stream);
+  double* w = static_cast<double*>(work);
+  fe_status st = dot1(x, y, n, w + 1024, w, s);
+  if (st != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(out_h, w + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
+fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_t n, void* stream) {
+  if (!x || !y || n < 0) return fail(FE_EINVAL, "fe_axpby: bad argument");
+  return axpby(alpha, x, beta, y, n, S(stream));
+}
+
+}  // extern "C"

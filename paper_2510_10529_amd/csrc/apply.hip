@@ -1,0 +1,394 @@
+// Matrix-free spectral-FE Kohn-Sham operator on node-major blocks (gfx950).
+//
+//   Y = alpha * ( (1/2) W^{-1/2} K W^{-1/2} X + (v - c - s_j) X ) + beta * Z
+//
+// The paper's operator (Eqs. 17, 19; Sec. 3.2.3) is a sum of per-cell dense
+// products K_e X_e followed by an assembly. On a tensor-product mesh the exact
+// element stiffness is K_e = (h/2)(K^ (x) M^ (x) M^ + M^ (x) K^ (x) M^ + M^ (x) M^ (x) K^)
+// (Eq. 12's basis is a tensor product), and the W^{-1/2} scaling factorises per
+// axis, so the assembled operator is
+//   K~ = K~1 (x) M~ (x) M~ + M~ (x) K~1 (x) M~ + M~ (x) M~ (x) K~1
+// with 1-D banded assembled matrices built from one scaled (p+1)x(p+1) element
+// pair (mt, kt). The kernel applies it by sum factorisation: six 1-D
+// contractions instead of one (p+1)^3 x (p+1)^3 dense product per cell, which
+// makes the apply bound by HBM instead of by FP64 matrix throughput.
+//
+// One workgroup owns an xy-tile of BXE x BYE cells (its nodes [e0 p, (e0+B) p) on
+// each axis), J consecutive columns of the block, and a range of cells along z,
+// which it marches through plane by plane:
+//   x-pass  (global -> LDS): U1 = M~x X, U2 = K~x X on the tile's rows plus the
+//                            y-halo, owner-computes (a vertex sums both cells);
+//   y-pass  (LDS -> LDS)   : A = M~y U1, B = M~y U2 + K~y U1 on owned nodes;
+//   z-step  (registers)    : each owned (x, y, j) column accumulates
+//                            M~z B + K~z A for the p+1 output planes of the
+//                            current cell and carries the shared top vertex
+//                            plane into the next cell.
+// Every output is written exactly once by its owner, so there are no atomics
+// and the result is bitwise reproducible. Dirichlet nodes are zero.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+namespace invdft {
+
+struct KParams {
+  const void* X;
+  void* Y;
+  const void* Z;
+  const double* v;
+  const double* colscale;   // device, nv entries, or null
+  int n, n1, nv, ld;
+  int zseg, tiles_x, tiles_y, jchunks, zsegs;
+  int has_colshift;
+  double alpha, beta, cshift;
+  double mt[kMaxP1 * kMaxP1];
+  double kt[kMaxP1 * kMaxP1];
+  double colshift[kMaxShiftCols];
+};
+
+template <int P>
+struct TileShape {
+  static constexpr int BE = (P <= 2) ? 4 : ((P <= 5) ? 2 : 1);  // cells per tile edge
+};
+
+// The scaled 1-D element matrices are symmetric and centrosymmetric
+// (A[i][k] = A[k][i] = A[P-i][P-k]: GLL nodes and weights are symmetric about
+// the cell centre). Indexing every entry through one canonical representative
+// lets the compiler keep only the distinct values (12 of 36 at P = 5) in scalar
+// registers; the host stores the average of the four copies there.
+__host__ __device__ constexpr int canon_index(int i, int k, int P) {
+  int a = i < k ? i : k, b = i < k ? k : i;
+  const int a2 = P - b, b2 = P - a;
+  if (a2 < a || (a2 == a && b2 < b)) {
+    a = a2;
+    b = b2;
+  }
+  return a * (P + 1) + b;
+}
+
+// Logical block order: column chunk fastest, then tile x, tile y, z-segment.
+// The hardware deals consecutive block ids round-robin to the 8 XCDs; this
+// remap gives each XCD a contiguous range of logical ids, so the column chunks
+// of one tile and its neighbour tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
+  const int q = nblk / 8, r = nblk % 8;
+  const int x = b % 8, i = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+template <typename T, int P, int J, int NT>
+__global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
+  using CT = T;  // compute type = storage type (FP64 or FP32)
+  constexpr int P1 = P + 1;
+  constexpr int BE = TileShape<P>::BE;
+  constexpr int BX = BE * P;              // owned nodes per tile edge
+  constexpr int NYI = (BE + 1) * P + 1;   // rows of the x-pass (owned + halo)
+  constexpr int NXI = BE * NYI * J;       // x-pass items
+  constexpr int XPT = (NXI + NT - 1) / NT;
+  constexpr int NYP = BX * BE * J;        // y-pass items
+  constexpr int NCOL = BX * BX * J;       // owned (x, y, column) z-columns
+  constexpr int CPT = (NCOL + NT - 1) / NT;
+
+  __shared__ CT sU1[2][NYI][BX][J];
+  __shared__ CT sU2[2][NYI][BX][J];
+  __shared__ CT sD[2][BX][BX][J];         // diagonal term (v - c - s_j) x of the plane
+  __shared__ CT sA[BX][BX][J];
+  __shared__ CT sB[BX][BX][J];
+
+  const T* __restrict__ X = static_cast<const T*>(prm.X);
+  T* Y = static_cast<T*>(prm.Y);  // may alias Z, never X
+  const T* Z = static_cast<const T*>(prm.Z);
+  const int tid = threadIdx.x;
+  const int n = prm.n, n1 = prm.n1, ld = prm.ld, nv = prm.nv;
+  const int pn = P * n;
+
+  int bid = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int jc = bid % prm.jchunks;
+  bid /= prm.jchunks;
+  const int tx = bid % prm.tiles_x;
+  bid /= prm.tiles_x;
+  const int ty = bid % prm.tiles_y;
+  const int zs = bid / prm.tiles_y;
+  const int ex0 = tx * BE, ey0 = ty * BE, j0 = jc * J;
+  const int ez0 = zs * prm.zseg;
+  const int ez1 = min(n, ez0 + prm.zseg);
+  const int ezs = (ez0 > 0) ? ez0 - 1 : 0;
+
+  auto node_ok = [&](int g) { return g >= 1 && g <= pn - 1; };
+  auto node_index = [&](int gx, int gy, int gz) -> long long {
+    return (long long)(gx - 1) + (long long)n1 * ((long long)(gy - 1) + (long long)n1 * (gz - 1));
+  };
+  auto MT = [&](int i, int k) { return (CT)prm.mt[canon_index(i, k, P)]; };
+  auto KT = [&](int i, int k) { return (CT)prm.kt[canon_index(i, k, P)]; };
+
+  // ---------------------------------------------------------------- x-item inputs
+  // x-item (jj, exl, yl): the 2P+1 nodes gx = ex P - P .. ex P + P of row gy, column j.
+  CT cur[XPT][2 * P + 1], nxt[XPT][2 * P + 1];
+  double vcur[XPT][P], vnxt[XPT][P];
+  auto load_items = [&](int gz, CT (*in)[2 * P + 1], double (*vv)[P]) {
+    const bool zok = node_ok(gz);
+#pragma unroll
+    for (int t = 0; t < XPT; ++t) {
+      const int item = tid + t * NT;
+      const int jj = item % J;
+      const int r = item / J;
+      const int exl = r % BE;
+      const int yl = r / BE;
+      const int gy = (ey0 - 1) * P + yl;
+      const int ex = ex0 + exl;
+      const int j = j0 + jj;
+      const bool rowok = item < NXI && zok && node_ok(gy) && j < nv;
+      const long long rowbase = rowok ? node_index(1, gy, gz) : 0;
+#pragma unroll
+      for (int k = 0; k <= 2 * P; ++k) {
+        const int gx = ex * P - P + k;
+        in[t][k] = (rowok && node_ok(gx)) ? X[(rowbase + gx - 1) * ld + j] : CT(0);
+      }
+      const bool own = rowok && yl >= P && yl < P + BX;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int gx = ex * P + i;
+        vv[t][i] = (own && node_ok(gx)) ? prm.v[rowbase + gx - 1] : 0.0;
+      }
+    }
+  };
+
+  // per-thread z-column accumulators: outputs of the P+1 planes of the current cell
+  CT acc[CPT][P1];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int i = 0; i <= P; ++i) acc[c][i] = 0;
+
+  const int gz0 = ezs * P, gz1 = ez1 * P;
+  load_items(gz0, cur, vcur);
+  int buf = 0;
+  const CT half = CT(0.5);
+#pragma unroll 1
+  for (int gz = gz0; gz <= gz1; ++gz) {
+    if (gz < gz1) load_items(gz + 1, nxt, vnxt);  // prefetch: in flight during this plane
+    // ---- x-pass: U1 = M~x X, U2 = K~x X on owned x, all NYI rows; diagonal term on owned rows
+#pragma unroll
+    for (int t = 0; t < XPT; ++t) {
+      const int item = tid + t * NT;
+      if (item >= NXI) continue;
+      const int jj = item % J;
+      const int r = item / J;
+      const int exl = r % BE;
+      const int yl = r / BE;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        CT u1 = 0, u2 = 0;
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+          u1 += MT(i, k) * cur[t][P + k];
+          u2 += KT(i, k) * cur[t][P + k];
+        }
+        if (i == 0) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) {  // left cell's row P (its node P is cur[t][P], already counted)
+            u1 += MT(P, k) * cur[t][k];
+            u2 += KT(P, k) * cur[t][k];
+          }
+          u1 += MT(P, P) * cur[t][P];
+          u2 += KT(P, P) * cur[t][P];
+        }
+        sU1[buf][yl][exl * P + i][jj] = u1;
+        sU2[buf][yl][exl * P + i][jj] = u2;
+      }
+      if (yl >= P && yl < P + BX) {
+        const int j = j0 + jj;
+        const double sh = prm.cshift + ((prm.has_colshift && j < nv) ? prm.colshift[j] : 0.0);
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          sD[buf][yl - P][exl * P + i][jj] = (CT)((vcur[t][i] - sh) * (double)cur[t][P + i]);
+      }
+    }
+    __syncthreads();
+    // ---- y-pass: A = M~y U1, B = M~y U2 + K~y U1 on owned nodes
+    for (int item = tid; item < NYP; item += NT) {
+      const int jj = item % J;
+      const int r = item / J;
+      const int xl = r % BX;
+      const int eyl = r / BX;
+      CT a1[2 * P + 1], a2[2 * P + 1];
+#pragma unroll
+      for (int k = 0; k <= 2 * P; ++k) {
+        a1[k] = sU1[buf][eyl * P + k][xl][jj];
+        a2[k] = sU2[buf][eyl * P + k][xl][jj];
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        CT A = 0, B = 0;
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+          A += MT(i, k) * a1[P + k];
+          B += MT(i, k) * a2[P + k] + KT(i, k) * a1[P + k];
+        }
+        if (i == 0) {
+#pragma unroll
+          for (int k = 0; k <= P; ++k) {
+            A += MT(P, k) * a1[k];
+            B += MT(P, k) * a2[k] + KT(P, k) * a1[k];
+          }
+        }
+        sA[eyl * P + i][xl][jj] = A;
+        sB[eyl * P + i][xl][jj] = B;
+      }
+    }
+    __syncthreads();
+    // ---- z-step: plane gz is node k of the current cell (k = 0 only for the first plane)
+    const int rel = gz - gz0;
+    const int k = (rel == 0) ? 0 : ((rel - 1) % P) + 1;
+    CT mcol[P1], kcol[P1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+      mcol[i] = half * (CT)prm.mt[canon_index(i, k, P)];
+      kcol[i] = half * (CT)prm.kt[canon_index(i, k, P)];
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int col = tid + c * NT;
+      if (col >= NCOL) continue;
+      const int jj = col % J;
+      const int xl = (col / J) % BX;
+      const int yl = col / (J * BX);
+      const CT a = sA[yl][xl][jj], b = sB[yl][xl][jj], d = sD[buf][yl][xl][jj];
+#pragma unroll
+      for (int i = 0; i <= P; ++i) acc[c][i] += mcol[i] * b + kcol[i] * a + (i == k ? d : CT(0));
+    }
+    if (k == P) {
+      // cell ez = (rel - 1) / P + ezs complete: planes ez P + i, i < P, are final
+      const int ez = (rel - 1) / P + ezs;
+      if (ez >= ez0) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int col = tid + c * NT;
+          if (col >= NCOL) continue;
+          const int jj = col % J;
+          const int xl = (col / J) % BX;
+          const int yl = col / (J * BX);
+          const int gx = ex0 * P + xl, gy = ey0 * P + yl, j = j0 + jj;
+          if (!node_ok(gx) || !node_ok(gy) || j >= nv) continue;
+          const CT scale = (CT)prm.alpha * (prm.colscale ? (CT)prm.colscale[j] : CT(1));
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            const int gzo = ez * P + i;
+            if (!node_ok(gzo)) continue;
+            const long long idx = node_index(gx, gy, gzo) * ld + j;
+            CT out = scale * acc[c][i];
+            if (Z) out += (CT)prm.beta * Z[idx];
+            Y[idx] = out;
+          }
+        }
+      }
+      // this vertex plane is also node 0 of the next cell
+      CT m0[P1], k0[P1];
+#pragma unroll
+      for (int i = 0; i <= P; ++i) {
+        m0[i] = half * MT(i, 0);
+        k0[i] = half * KT(i, 0);
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int col = tid + c * NT;
+        CT a = 0, b = 0;
+        if (col < NCOL) {
+          const int jj = col % J;
+          const int xl = (col / J) % BX;
+          const int yl = col / (J * BX);
+          a = sA[yl][xl][jj];
+          b = sB[yl][xl][jj];
+        }
+        const CT carry = acc[c][P];
+#pragma unroll
+        for (int i = 0; i <= P; ++i) acc[c][i] = (i == 0 ? carry : CT(0)) + m0[i] * b + k0[i] * a;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < XPT; ++t) {
+#pragma unroll
+      for (int q = 0; q <= 2 * P; ++q) cur[t][q] = nxt[t][q];
+#pragma unroll
+      for (int q = 0; q < P; ++q) vcur[t][q] = vnxt[t][q];
+    }
+    buf ^= 1;
+  }
+}
+
+namespace {
+
+template <typename T, int P, int J>
+fe_status launch_typed(const Mesh& m, KParams& prm, hipStream_t s) {
+  constexpr int NT = 512;
+  constexpr int BE = TileShape<P>::BE;
+  prm.tiles_x = (m.n + BE - 1) / BE;
+  prm.tiles_y = prm.tiles_x;
+  prm.jchunks = (prm.nv + J - 1) / J;
+  const long long base = (long long)prm.tiles_x * prm.tiles_y * prm.jchunks;
+  // enough workgroups to fill 256 CUs several times; each z-segment re-walks one
+  // extra cell to pick up the shared bottom vertex plane
+  int zsegs = (int)std::min<long long>(m.n, std::max<long long>(1, (2048 + base - 1) / base));
+  int zseg = (m.n + zsegs - 1) / zsegs;
+  zseg = std::max(zseg, std::min(m.n, 4));
+  zsegs = (m.n + zseg - 1) / zseg;
+  prm.zseg = zseg;
+  prm.zsegs = zsegs;
+  const long long grid = base * zsegs;
+  if (grid > 0x7fffffffLL) return fail(FE_EINVAL, "ks_apply: problem too large for one launch");
+  hipLaunchKernelGGL((ks_apply_kernel<T, P, J, NT>), dim3((unsigned)grid), dim3(NT), 0, s, prm);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T, int J>
+fe_status launch_p(const Mesh& m, KParams& prm, hipStream_t s) {
+  switch (m.p) {
+    case 1: return launch_typed<T, 1, J>(m, prm, s);
+    case 2: return launch_typed<T, 2, J>(m, prm, s);
+    case 3: return launch_typed<T, 3, J>(m, prm, s);
+    case 4: return launch_typed<T, 4, J>(m, prm, s);
+    case 5: return launch_typed<T, 5, J>(m, prm, s);
+    case 6: return launch_typed<T, 6, J>(m, prm, s);
+    case 7: return launch_typed<T, 7, J>(m, prm, s);
+    case 8: return launch_typed<T, 8, J>(m, prm, s);
+    default: return fail(FE_EINVAL, "ks_apply: unsupported order p");
+  }
+}
+
+}  // namespace
+
+fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s) {
+  KParams prm;
+  std::memset(&prm, 0, sizeof(prm));
+  prm.X = a.X;
+  prm.Y = a.Y;
+  prm.Z = a.Z;
+  prm.v = a.v;
+  prm.colscale = a.d_colscale;
+  prm.n = m.n;
+  prm.n1 = m.n1;
+  prm.nv = a.nv;
+  prm.ld = a.ld;
+  prm.alpha = a.alpha;
+  prm.beta = a.beta;
+  prm.cshift = a.cshift;
+  std::memcpy(prm.mt, m.mt, sizeof(prm.mt));
+  std::memcpy(prm.kt, m.kt, sizeof(prm.kt));
+  if (a.colshift) {
+    if (a.nv > kMaxShiftCols) return fail(FE_EINVAL, "ks_apply: per-column shifts limited to 256 columns");
+    prm.has_colshift = 1;
+    for (int j = 0; j < a.nv; ++j) prm.colshift[j] = a.colshift[j];
+  }
+  if (m.nf == 0) return FE_OK;
+  switch (prec) {
+    case FE_F64: return launch_p<double, 8>(m, prm, s);
+    case FE_F32: return launch_p<float, 16>(m, prm, s);
+    default: return fail(FE_EINVAL, "ks_apply: precision not supported by this operator");
+  }
+}
+
+}  // namespace invdft

@@ -1,0 +1,443 @@
+// Tall-skinny block operations on node-major blocks (gfx950).
+//
+// Gram products X^T Y and rotations X C of N x nv blocks (nv <= 64 per tile)
+// are dense contractions, so they run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): each wavefront streams 4 rows per instruction
+// straight from HBM into the A/B operands (16 consecutive doubles of a row per
+// quarter-wave, i.e. 128-byte coalesced loads) and keeps the 16x16 output tiles
+// in accumulation registers. Reductions over rows are written as per-workgroup
+// partials and summed in a fixed order by a second kernel, so every result is
+// bitwise reproducible (no floating-point atomics anywhere).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace invdft {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ double ld_d(const T* p) {
+  return (double)(*p);
+}
+
+// MFMA FP64 16x16x4 operand layout on gfx950 (checked on the device): lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the 16x16 result D is held as D[l/16 + 4r][l%16]
+// in register r (rows interleaved across the four lane groups).
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGramThreads = 256;
+constexpr int kGramTile = 64;  // output tile edge handled by one workgroup (4 x 4 MFMA tiles)
+
+// partial[blk][i][j] (for this output tile) = sum over the block's rows of X[r][i] Y[r][j].
+template <typename T>
+__global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(const T* __restrict__ X, int ldx,
+                                                                    const T* __restrict__ Y, int ldy,
+                                                                    long long N, int nx, int ny,
+                                                                    long long rows_per_blk, int sym,
+                                                                    double* __restrict__ partial) {
+  __shared__ double red[kGramTile * kGramTile];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tiles_j = (ny + kGramTile - 1) / kGramTile;
+  const int i0 = (blockIdx.y / tiles_j) * kGramTile;
+  const int j0 = (blockIdx.y % tiles_j) * kGramTile;
+  const long long r_begin = (long long)blockIdx.x * rows_per_blk;
+  const long long r_end = min(N, r_begin + rows_per_blk);
+  const int li = lane & 15, lk = lane >> 4;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+
+  const bool symtile = sym && (i0 == j0);
+  // each wave takes every 4th group of 4 rows
+  for (long long r0 = r_begin + 4 * wave; r0 < r_end; r0 += 4 * (kGramThreads / 64)) {
+    const long long r = r0 + lk;
+    const bool rok = r < r_end;
+    double av[4], bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ci = i0 + 16 * t + li;
+      const int cj = j0 + 16 * t + li;
+      av[t] = (rok && ci < nx) ? ld_d(X + r * ldx + ci) : 0.0;
+      bv[t] = (rok && cj < ny) ? ld_d(Y + r * ldy + cj) : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (symtile && b < a) continue;
+        acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+      }
+  }
+  // reduce the 4 waves through LDS in a fixed order
+  for (int w = 0; w < kGramThreads / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = 16 * a + lk + 4 * rr;
+            const int j = 16 * b + li;
+            const double val = acc[a][b][rr];
+            if (w == 0)
+              red[i * kGramTile + j] = val;
+            else
+              red[i * kGramTile + j] += val;
+          }
+    }
+    __syncthreads();
+  }
+  // write the partial (full tile; symmetric tiles mirror the upper part)
+  double* out = partial + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * kGramTile * kGramTile;
+  for (int e = threadIdx.x; e < kGramTile * kGramTile; e += kGramThreads) {
+    const int i = e / kGramTile, j = e % kGramTile;
+    double val = red[e];
+    if (symtile && (j / 16) < (i / 16)) val = red[j * kGramTile + i];
+    out[e] = val;
+  }
+}
+
+// out[i][j] = sum over blocks (fixed order) of the partial tiles.
+__global__ void gram_reduce_kernel(const double* __restrict__ partial, int nblk, int ntiles, int nx, int ny,
+                                   double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nx * ny) return;
+  const int i = e / ny, j = e % ny;
+  const int tiles_j = (ny + kGramTile - 1) / kGramTile;
+  const int tile = (i / kGramTile) * tiles_j + (j / kGramTile);
+  const int off = (i % kGramTile) * kGramTile + (j % kGramTile);
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[((long long)b * ntiles + tile) * kGramTile * kGramTile + off];
+  out[e] = s;
+}
+
+int gram_blocks(long long N) {
+  long long b = (N + 511) / 512;
+  return (int)std::max<long long>(1, std::min<long long>(b, 1024));
+}
+
+// out = alpha * (A C) + beta * Xin  over N rows; A: N x nin (lda), C: nin x nout (row-major, device),
+// Xin/out: N x nout (ldo). Each wave owns 16 rows and all nout (<= 64) columns; out may alias Xin.
+template <typename T>
+__global__ __launch_bounds__(256) void rotate_kernel(const T* A, int lda, long long N, int nin,
+                                                     const double* __restrict__ C, int nout, double alpha,
+                                                     double beta, const T* Xin, T* out, int ldo) {
+  __shared__ double sC[64 * 64];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int k = e / 64, j = e % 64;
+    sC[e] = (k < nin && j < nout) ? C[k * nout + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const long long r0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  if (r0 >= N) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tiles = (nout + 15) / 16;
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+  // D[i = row][j = out col] = sum_k A[row][k] C[k][j]; A operand lane holds A[r0 + li][k0 + lk]
+  const long long ra = r0 + li;
+  const bool raok = ra < N;
+  for (int k0 = 0; k0 < nin; k0 += 4) {
+    const int k = k0 + lk;
+    const double av = (raok && k < nin) ? ld_d(A + ra * lda + k) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < tiles) acc[t] = mfma16(av, sC[(k < 64 ? k : 0) * 64 + 16 * t + li], acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= tiles) continue;
+    const int j = 16 * t + li;
+    if (j >= nout) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const long long row = r0 + lk + 4 * rr;
+      if (row >= N) continue;
+      double val = alpha * acc[t][rr];
+      if (beta != 0.0) val += beta * ld_d(Xin + row * ldo + j);
+      out[row * ldo + j] = (T)val;
+    }
+  }
+}
+
+// Column dot products: partial[blk][j] = sum over the block's rows of X[r][j] Y[r][j].
+template <typename T>
+__global__ __launch_bounds__(256) void coldot_partial_kernel(const T* __restrict__ X, const T* __restrict__ Y,
+                                                             int ld, long long N, int nv, long long rows_per_blk,
+                                                             double* __restrict__ partial) {
+  __shared__ double red[256];
+  const long long r_begin = (long long)blockIdx.x * rows_per_blk;
+  const long long r_end = min(N, r_begin + rows_per_blk);
+  const int j = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int rsub = threadIdx.x >> 6;
+  double s = 0.0;
+  if (j < nv)
+    for (long long r = r_begin + rsub; r < r_end; r += 4) s += ld_d(X + r * ld + j) * ld_d(Y + r * ld + j);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && j < nv) {
+    const double t = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+    partial[(long long)blockIdx.x * nv + j] = t;
+  }
+}
+
+// Residual column norms: partial[blk][j] = sum over rows of (HX[r][j] - lam_j X[r][j])^2.
+__global__ __launch_bounds__(256) void resid_partial_kernel(const double* __restrict__ HX, const double* __restrict__ X,
+                                                            const double* __restrict__ lam, int ld, long long N,
+                                                            int nv, long long rows_per_blk,
+                                                            double* __restrict__ partial) {
+  __shared__ double red[256];
+  const long long r_begin = (long long)blockIdx.x * rows_per_blk;
+  const long long r_end = min(N, r_begin + rows_per_blk);
+  const int j = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int rsub = threadIdx.x >> 6;
+  double s = 0.0;
+  if (j < nv) {
+    const double l = lam[j];
+    for (long long r = r_begin + rsub; r < r_end; r += 4) {
+      const double d = HX[r * ld + j] - l * X[r * ld + j];
+      s += d * d;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && j < nv) {
+    const double t = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+    partial[(long long)blockIdx.x * nv + j] = t;
+  }
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nv + j];
+  out[j] = s;
+}
+
+__global__ void dot1_partial_kernel(const double* __restrict__ x, const double* __restrict__ y, long long n,
+                                    long long per_blk, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const long long b0 = (long long)blockIdx.x * per_blk;
+  const long long b1 = min(n, b0 + per_blk);
+  double s = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += 256) s += x[i] * y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void max1_partial_kernel(const double* __restrict__ x, long long n, long long per_blk,
+                                    double* __restrict__ partial) {
+  __shared__ double red[256];
+  const long long b0 = (long long)blockIdx.x * per_blk;
+  const long long b1 = min(n, b0 + per_blk);
+  double s = -1.0e300;
+  for (long long i = b0 + threadIdx.x; i < b1; i += 256) s = fmax(s, x[i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void reduce_serial_kernel(const double* __restrict__ partial, int nblk, int op, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = (op == 0) ? 0.0 : -1.0e300;
+  for (int b = 0; b < nblk; ++b) s = (op == 0) ? s + partial[b] : fmax(s, partial[b]);
+  *out = s;
+}
+
+template <typename TS, typename TD>
+__global__ void cast_kernel(const TS* __restrict__ src, TD* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (TD)src[i];
+}
+
+__global__ void axpby_kernel(double alpha, const double* __restrict__ x, double beta, double* __restrict__ y,
+                             long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = alpha * x[i] + beta * y[i];
+}
+
+__global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = val;
+}
+
+unsigned stream_grid(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+size_t gram_work_bytes(int64_t N, int nx, int ny) {
+  const int tiles = ((nx + kGramTile - 1) / kGramTile) * ((ny + kGramTile - 1) / kGramTile);
+  return (size_t)gram_blocks(N) * tiles * kGramTile * kGramTile * sizeof(double);
+}
+
+fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx, int ny, bool f32, double* out,
+               void* work, hipStream_t s) {
+  if (nx <= 0 || ny <= 0) return FE_OK;
+  const int nblk = gram_blocks(N);
+  const int tiles_i = (nx + kGramTile - 1) / kGramTile, tiles_j = (ny + kGramTile - 1) / kGramTile;
+  const long long rpb = (N + nblk - 1) / nblk;
+  const int sym = (X == Y && ldx == ldy && nx == ny) ? 1 : 0;
+  double* partial = static_cast<double*>(work);
+  dim3 grid(nblk, tiles_i * tiles_j);
+  if (f32)
+    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(kGramThreads), 0, s, static_cast<const float*>(X), ldx,
+                       static_cast<const float*>(Y), ldy, (long long)N, nx, ny, rpb, sym, partial);
+  else
+    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(kGramThreads), 0, s, static_cast<const double*>(X),
+                       ldx, static_cast<const double*>(Y), ldy, (long long)N, nx, ny, rpb, sym, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 255) / 256), dim3(256), 0, s, partial, nblk,
+                     tiles_i * tiles_j, nx, ny, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* out, int ldo,
+                 hipStream_t s) {
+  if (nin > 64 || nout > 64) return fail(FE_EINVAL, "rotate: blocks wider than 64 columns are not supported");
+  if (N <= 0) return FE_OK;
+  const unsigned grid = (unsigned)((N + 63) / 64);
+  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, 1.0, 0.0,
+                     (const double*)nullptr, out, ldo);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+size_t coldot_work_bytes(int64_t N, int nv) { return (size_t)gram_blocks(N) * nv * sizeof(double); }
+
+fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f32, double* out, void* work,
+                 hipStream_t s) {
+  const int nblk = gram_blocks(N);
+  const long long rpb = (N + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  dim3 grid(nblk, (nv + 63) / 64);
+  if (f32)
+    hipLaunchKernelGGL(coldot_partial_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(X),
+                       static_cast<const float*>(Y), ld, (long long)N, nv, rpb, partial);
+  else
+    hipLaunchKernelGGL(coldot_partial_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(X),
+                       static_cast<const double*>(Y), ld, (long long)N, nv, rpb, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status colresid(const double* HX, const double* X, const double* lam, int ld, int64_t N, int nv, double* out,
+                   void* work, hipStream_t s) {
+  const int nblk = gram_blocks(N);
+  const long long rpb = (N + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  hipLaunchKernelGGL(resid_partial_kernel, dim3(nblk, (nv + 63) / 64), dim3(256), 0, s, HX, X, lam, ld, (long long)N,
+                     nv, rpb, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status dot1(const double* x, const double* y, int64_t n, double* out, void* work, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((n + 4095) / 4096, 1024));
+  const long long per = (n + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  hipLaunchKernelGGL(dot1_partial_kernel, dim3(nblk), dim3(256), 0, s, x, y, (long long)n, per, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_serial_kernel, dim3(1), dim3(64), 0, s, partial, nblk, 0, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((n + 4095) / 4096, 1024));
+  const long long per = (n + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  hipLaunchKernelGGL(max1_partial_kernel, dim3(nblk), dim3(256), 0, s, x, (long long)n, per, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_serial_kernel, dim3(1), dim3(64), 0, s, partial, nblk, 1, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status copy_block(const double* src, double* dst, int64_t count, hipStream_t s) {
+  INVDFT_HIP(hipMemcpyAsync(dst, src, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return FE_OK;
+}
+
+fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL((cast_kernel<double, float>), dim3(stream_grid(count)), dim3(256), 0, s, src, dst,
+                     (long long)count);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL((cast_kernel<float, double>), dim3(stream_grid(count)), dim3(256), 0, s, src, dst,
+                     (long long)count);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(stream_grid(n)), dim3(256), 0, s, alpha, x, beta, y, (long long)n);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status fill(double* y, double val, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(stream_grid(n)), dim3(256), 0, s, y, val, (long long)n);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+size_t project_work_bytes(int64_t N, int k, int nv) {
+  return gram_work_bytes(N, k, nv) + (size_t)k * nv * sizeof(double) + 256;
+}
+
+fe_status project_out(const double* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s) {
+  if (k > 64 || nv > 64) return fail(FE_EINVAL, "projection: blocks wider than 64 columns are not supported");
+  if (f32) return fail(FE_EINVAL, "projection: FP32 blocks use the float projection");
+  char* w = static_cast<char*>(work);
+  double* G = reinterpret_cast<double*>(w);
+  void* gw = w + (((size_t)k * nv * sizeof(double) + 255) / 256) * 256;
+  fe_status st = gram(Psi, k, X, nv, N, k, nv, false, G, gw, s);
+  if (st != FE_OK) return st;
+  const unsigned grid = (unsigned)((N + 63) / 64);
+  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, Psi, k, (long long)N, k, G, nv, -1.0, 1.0,
+                     static_cast<const double*>(X), static_cast<double*>(X), nv);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+}  // namespace invdft

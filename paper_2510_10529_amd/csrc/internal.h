@@ -1,0 +1,104 @@
+// Internal declarations of the gfx950 inverse-DFT library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "invdft.h"
+
+namespace invdft {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxP1 = kMaxP + 1;
+constexpr int kMaxShiftCols = 256;
+
+// Mesh handle: immutable after creation.
+struct Mesh {
+  int p = 0, n = 0, n1 = 0;   // order, cells per axis, free nodes per axis (p n - 1)
+  double L = 0, h = 0;
+  int64_t nf = 0;             // free nodes
+  double kin_bound = 0;       // Fried element bound on lambda_max(K~/2)
+  // 1-D element matrices scaled by the assembled W1^{-1/2} at the element's
+  // local nodes (identical for every element of the uniform mesh), row-major
+  // (p+1) x (p+1): mt = s (h/2) M^ s, kt = s (2/h) K^ s.
+  double mt[kMaxP1 * kMaxP1] = {};
+  double kt[kMaxP1 * kMaxP1] = {};
+  std::vector<double> x1, w1, kd1, md1;  // per free 1-D node: coordinate, W1, diag(K~1), diag(M~1)
+  int device = 0;
+  double* d_x1 = nullptr;     // device copies of the 1-D tables (n1 each)
+  double* d_w1 = nullptr;
+  double* d_kd1 = nullptr;
+  double* d_md1 = nullptr;
+};
+
+// thread-local error text
+void set_error(const std::string& msg);
+fe_status fail(fe_status st, const std::string& msg);
+fe_status hip_fail(hipError_t e, const char* what);
+
+#define INVDFT_HIP(call)                                      \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::invdft::hip_fail(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- host math
+void gll_rule(int p, double* x, double* w);                  // p+1 GLL nodes/weights
+void gauss_rule(int m, double* x, double* w);                // m Gauss-Legendre nodes/weights
+void reference_matrices(int p, double* Kh, double* Mh, double* xi, double* wi);
+bool cholesky_lower(int n, double* A);                       // A = L L^T in place (lower), row-major
+void invert_lower(int n, const double* L, double* Linv);     // row-major
+void jacobi_eigh(int n, double* A, double* evals, double* evecs);  // ascending; evecs columns, row-major
+double max_eig_sym(int n, const double* A);
+
+// ---------------------------------------------------------------- kernels
+// Apply parameters; Y = alpha (K~/2 X + (v - cshift - colshift_j) X) + beta Z.
+struct ApplyArgs {
+  const void* X;
+  void* Y;
+  const void* Z;
+  const double* v;
+  int nv, ld;
+  double alpha, beta, cshift;
+  const double* colshift;     // host array (nv) or nullptr; copied into kernel arguments
+  const double* d_colscale;   // device array (nv) or nullptr: output column j scaled by it
+};
+fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
+
+// Block operations (FP64 reductions; T = double or float storage).
+// Gram: out (nx x ny, row-major, FP64 device) = X^T Y over the first N rows.
+size_t gram_work_bytes(int64_t N, int nx, int ny);
+fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx, int ny, bool f32,
+               double* out, void* work, hipStream_t s);
+// out[a, j] = sum_k X[a, k] C[k, j] (C FP64 device, nin x nout, row-major); out may equal X.
+fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* out,
+                 int ldo, hipStream_t s);
+// Column-wise dot products d_j = sum_a X[a,j] Y[a,j] (FP64 result, device array nv).
+size_t coldot_work_bytes(int64_t N, int nv);
+fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f32, double* out, void* work,
+                 hipStream_t s);
+// out[j] = sum_a (HX[a,j] - lam_j X[a,j])^2 (lam on device); work: coldot_work_bytes.
+fe_status colresid(const double* HX, const double* X, const double* lam, int ld, int64_t N, int nv, double* out,
+                   void* work, hipStream_t s);
+// out[j] = sum_b partial[b * nv + j] in block order (deterministic).
+fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s);
+// Scalar dot product of two FP64 vectors (device result).
+fe_status dot1(const double* x, const double* y, int64_t n, double* out, void* work, hipStream_t s);
+fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t s);
+
+// Kernels used by the Krylov and loss/gradient code (defined in blockops.hip).
+fe_status copy_block(const double* src, double* dst, int64_t count, hipStream_t s);
+fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
+fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s);
+fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s);
+fe_status fill(double* y, double val, int64_t n, hipStream_t s);
+
+// Projection X <- X - Psi (Psi^T X) (Psi: N x k, ld k; X: N x nv, ld nv). work: gram work + k*nv.
+size_t project_work_bytes(int64_t N, int k, int nv);
+fe_status project_out(const double* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work,
+                      hipStream_t s);
+
+}  // namespace invdft

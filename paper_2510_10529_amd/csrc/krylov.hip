@@ -1,0 +1,426 @@
+// Density, loss, adjoint right-hand side, gradient (Eqs. 1, 4, 7, 10, 11, 22)
+// and the vector/scalar kernels of the batched projected MINRES adjoint solve
+// (Sec. 3.2.2; Paige and Saunders 1975). Blocks are node-major, one column per
+// occupied orbital; all per-column MINRES scalars live on the device, so an
+// iteration makes no host round trip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "krylov.h"
+
+namespace invdft {
+
+namespace {
+
+unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 16384)); }
+
+__device__ __forceinline__ void node_xyz(long long a, int n1, int* ix, int* iy, int* iz) {
+  const long long n1l = n1;
+  *ix = (int)(a % n1l);
+  const long long r = a / n1l;
+  *iy = (int)(r % n1l);
+  *iz = (int)(r / n1l);
+}
+
+__global__ void nodes_kernel(const double* __restrict__ x1, const double* __restrict__ w1, int n1, long long nf,
+                             double* __restrict__ xyz, double* __restrict__ w) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_xyz(a, n1, &ix, &iy, &iz);
+    if (xyz) {
+      xyz[3 * a + 0] = x1[ix];
+      xyz[3 * a + 1] = x1[iy];
+      xyz[3 * a + 2] = x1[iz];
+    }
+    if (w) w[a] = w1[ix] * w1[iy] * w1[iz];
+  }
+}
+
+// diag(K~/2)_a = (kd(x) md(y) md(z) + md(x) kd(y) md(z) + md(x) md(y) kd(z)) / 2
+__global__ void kdiag_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
+                             double* __restrict__ d) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_xyz(a, n1, &ix, &iy, &iz);
+    d[a] = 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
+  }
+}
+
+struct Occ {
+  double f[kMaxShiftCols];
+};
+
+// rho_a = sum_i f_i psi_{a,i}^2 / W_a   (Eq. 4)
+__global__ void density_kernel(const double* __restrict__ Psi, int nocc, Occ occ, const double* __restrict__ w1,
+                               int n1, long long nf, double* __restrict__ rho) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_xyz(a, n1, &ix, &iy, &iz);
+    const double* row = Psi + a * nocc;
+    double s = 0.0;
+    for (int i = 0; i < nocc; ++i) s += occ.f[i] * row[i] * row[i];
+    rho[a] = s / (w1[ix] * w1[iy] * w1[iz]);
+  }
+}
+
+// partial sums of W_a (rho_data,a - rho_a)^2   (Eq. 1, w = 1)
+__global__ void loss_partial_kernel(const double* __restrict__ rho, const double* __restrict__ rho_d,
+                                    const double* __restrict__ w1, int n1, long long nf, long long per,
+                                    double* __restrict__ partial) {
+  __shared__ double red[256];
+  const long long b0 = (long long)blockIdx.x * per;
+  const long long b1 = min(nf, b0 + per);
+  double s = 0.0;
+  for (long long a = b0 + threadIdx.x; a < b1; a += 256) {
+    int ix, iy, iz;
+    node_xyz(a, n1, &ix, &iy, &iz);
+    const double d = rho_d[a] - rho[a];
+    s += w1[ix] * w1[iy] * w1[iz] * d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_serial_kernel(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b];
+    *out = s;
+  }
+}
+
+// R[a, i] = -4 f_i (rho_a - rho_data,a) psi_{a,i}   (the unprojected adjoint source, Eq. 7)
+__global__ void rhs_kernel(const double* __restrict__ Psi, int nocc, Occ occ, const double* __restrict__ rho,
+                           const double* __restrict__ rho_d, long long nf, double* __restrict__ R) {
+  const long long total = nf * nocc;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long a = e / nocc;
+    const int i = (int)(e % nocc);
+    R[e] = -4.0 * occ.f[i] * (rho[a] - rho_d[a]) * Psi[e];
+  }
+}
+
+// grad_b = sum_i psi_{b,i} q_{b,i}, zeroed where rho_data < tau   (Eqs. 11, 22; Sec. 3.1.2)
+__global__ void grad_kernel(const double* __restrict__ Psi, const double* __restrict__ Q, int nocc,
+                            const double* __restrict__ rho_d, double tau, long long nf, double* __restrict__ g) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nocc; ++i) s += Psi[a * nocc + i] * Q[a * nocc + i];
+    if (tau > 0.0 && rho_d && rho_d[a] < tau) s = 0.0;
+    g[a] = s;
+  }
+}
+
+// ------------------------------------------------------------------ MINRES
+// per-column scalar state (struct of arrays, each of length k)
+enum {
+  S_BETA = 0, S_OLDB, S_DBAR, S_EPSLN, S_PHIBAR, S_BETA1, S_CS, S_SN, S_ALFA, S_C1, S_C2,
+  S_INVBETA, S_INVBETA_OLD, S_OLDEPS, S_DELTA, S_INVGAMMA, S_PHI, S_ACTIVE, S_ITERS, S_RELRES, S_D1, S_D2,
+  S_COUNT
+};
+
+template <typename T>
+__global__ void mr_init_kernel(double* __restrict__ st, const double* __restrict__ dot_r_z, int k) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double* s = st;
+  const double b1 = sqrt(fmax(dot_r_z[j], 0.0));
+  s[S_BETA * k + j] = b1;
+  s[S_BETA1 * k + j] = b1;
+  s[S_OLDB * k + j] = 0.0;
+  s[S_DBAR * k + j] = 0.0;
+  s[S_EPSLN * k + j] = 0.0;
+  s[S_PHIBAR * k + j] = b1;
+  s[S_CS * k + j] = -1.0;
+  s[S_SN * k + j] = 0.0;
+  s[S_INVBETA * k + j] = b1 > 0.0 ? 1.0 / b1 : 0.0;
+  s[S_INVBETA_OLD * k + j] = 0.0;
+  s[S_ACTIVE * k + j] = b1 > 0.0 ? 1.0 : 0.0;
+  s[S_ITERS * k + j] = 0.0;
+  s[S_RELRES * k + j] = b1 > 0.0 ? 1.0 : 0.0;
+  s[S_C1 * k + j] = 0.0;
+  s[S_C2 * k + j] = 0.0;
+  s[S_PHI * k + j] = 0.0;
+}
+
+// after the two dots d1 = z.y / beta (= v.y) and d2 = z.r1 / beta (= v.r1):
+// alfa = v.(y - c1 r1) = d1 - c1 d2, c2 = alfa / beta
+__global__ void mr_alfa_kernel(double* __restrict__ st, const double* __restrict__ d1, const double* __restrict__ d2,
+                               int k, int first) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double* s = st;
+  const double beta = s[S_BETA * k + j];
+  const double ib = s[S_INVBETA * k + j];
+  const double c1 = first ? 0.0 : beta / s[S_OLDB * k + j];
+  const double alfa = ib * d1[j] - c1 * ib * d2[j];
+  s[S_C1 * k + j] = (s[S_ACTIVE * k + j] > 0.0) ? c1 : 0.0;
+  s[S_ALFA * k + j] = alfa;
+  s[S_C2 * k + j] = (s[S_ACTIVE * k + j] > 0.0) ? alfa * ib : 0.0;
+}
+
+// Givens update after beta_new^2 = r2.z_new (Paige-Saunders recurrences).
+__global__ void mr_givens_kernel(double* __restrict__ st, const double* __restrict__ dot_r_z, int k, double tol) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double* s = st;
+  if (!(s[S_ACTIVE * k + j] > 0.0)) {
+    s[S_PHI * k + j] = 0.0;
+    s[S_INVGAMMA * k + j] = 0.0;
+    s[S_OLDEPS * k + j] = 0.0;
+    s[S_DELTA * k + j] = 0.0;
+    s[S_INVBETA_OLD * k + j] = 0.0;
+    return;
+  }
+  const double alfa = s[S_ALFA * k + j];
+  const double oldb_new = s[S_BETA * k + j];
+  const double beta = sqrt(fmax(dot_r_z[j], 0.0));
+  const double cs = s[S_CS * k + j], sn = s[S_SN * k + j];
+  const double dbar = s[S_DBAR * k + j];
+  const double oldeps = s[S_EPSLN * k + j];
+  const double delta = cs * dbar + sn * alfa;
+  const double gbar = sn * dbar - cs * alfa;
+  const double epsln = sn * beta;
+  const double dbar_new = -cs * beta;
+  double gamma = sqrt(gbar * gbar + beta * beta);
+  gamma = fmax(gamma, 1e-300);
+  const double cs_new = gbar / gamma, sn_new = beta / gamma;
+  const double phibar = s[S_PHIBAR * k + j];
+  const double phi = cs_new * phibar;
+  const double phibar_new = sn_new * phibar;
+  s[S_OLDB * k + j] = oldb_new;
+  s[S_INVBETA_OLD * k + j] = s[S_INVBETA * k + j];
+  s[S_BETA * k + j] = beta;
+  s[S_INVBETA * k + j] = beta > 0.0 ? 1.0 / beta : 0.0;
+  s[S_CS * k + j] = cs_new;
+  s[S_SN * k + j] = sn_new;
+  s[S_DBAR * k + j] = dbar_new;
+  s[S_EPSLN * k + j] = epsln;
+  s[S_OLDEPS * k + j] = oldeps;
+  s[S_DELTA * k + j] = delta;
+  s[S_INVGAMMA * k + j] = 1.0 / gamma;
+  s[S_PHI * k + j] = phi;
+  s[S_PHIBAR * k + j] = phibar_new;
+  s[S_ITERS * k + j] += 1.0;
+  const double rel = phibar_new / s[S_BETA1 * k + j];
+  s[S_RELRES * k + j] = rel;
+  if (rel <= tol || beta == 0.0) s[S_ACTIVE * k + j] = 0.0;
+}
+
+// d1 = z.y and d2 = z.r1 column-wise partials (two dots in one pass)
+__global__ __launch_bounds__(256) void mr_dots_kernel(const double* __restrict__ z, const double* __restrict__ y,
+                                                      const double* __restrict__ r1, int k, long long nf,
+                                                      long long per, double* __restrict__ p1,
+                                                      double* __restrict__ p2) {
+  __shared__ double red1[256], red2[256];
+  const long long b0 = (long long)blockIdx.x * per;
+  const long long b1 = min(nf, b0 + per);
+  const int j = threadIdx.x % 64;
+  const int sub = threadIdx.x / 64;
+  double s1 = 0.0, s2 = 0.0;
+  if (j < k)
+    for (long long a = b0 + sub; a < b1; a += 4) {
+      const double zz = z[a * k + j];
+      s1 += zz * y[a * k + j];
+      s2 += zz * r1[a * k + j];
+    }
+  red1[threadIdx.x] = s1;
+  red2[threadIdx.x] = s2;
+  __syncthreads();
+  if (threadIdx.x < 64 && j < k) {
+    p1[(long long)blockIdx.x * k + j] = ((red1[j] + red1[j + 64]) + red1[j + 128]) + red1[j + 192];
+    p2[(long long)blockIdx.x * k + j] = ((red2[j] + red2[j + 64]) + red2[j + 128]) + red2[j + 192];
+  }
+}
+
+// rnew = y - c1 r1 - c2 r2 (stored over r1) ; u = rnew / D (stored over y)
+__global__ void mr_resid_precond_kernel(double* __restrict__ y, double* __restrict__ r1,
+                                        const double* __restrict__ r2, const double* __restrict__ st,
+                                        const double* __restrict__ dinv, int k, long long nf) {
+  const long long total = nf * k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % k);
+    const long long a = e / k;
+    if (!(st[S_ACTIVE * k + j] > 0.0)) continue;
+    const double rn = y[e] - st[S_C1 * k + j] * r1[e] - st[S_C2 * k + j] * r2[e];
+    r1[e] = rn;
+    y[e] = rn * dinv[a];
+  }
+}
+
+// w_new = (z_old / beta_old - oldeps w1 - delta w2) / gamma ; x += phi w_new  (w_new stored over w1)
+__global__ void mr_update_kernel(const double* __restrict__ zold, double* __restrict__ w1,
+                                 const double* __restrict__ w2, double* __restrict__ x,
+                                 const double* __restrict__ st, int k, long long nf) {
+  const long long total = nf * k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % k);
+    const double ig = st[S_INVGAMMA * k + j];
+    if (ig == 0.0) continue;  // frozen column (converged before this step)
+    const double wn = (zold[e] * st[S_INVBETA_OLD * k + j] - st[S_OLDEPS * k + j] * w1[e] - st[S_DELTA * k + j] * w2[e]) * ig;
+    w1[e] = wn;
+    x[e] += st[S_PHI * k + j] * wn;
+  }
+}
+
+__global__ void dinv_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
+                            double* __restrict__ dinv) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_xyz(a, n1, &ix, &iy, &iz);
+    const double d = 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
+    dinv[a] = 1.0 / d;
+  }
+}
+
+// y = x / D row-wise (block)
+__global__ void precond_kernel(const double* __restrict__ x, const double* __restrict__ dinv, int k, long long nf,
+                               double* __restrict__ y) {
+  const long long total = nf * k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
+    y[e] = x[e] * dinv[e / k];
+}
+
+// r = b - r (in place): residual from r = A q
+__global__ void sub_from_kernel(const double* __restrict__ b, double* __restrict__ r, long long total) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
+    r[e] = b[e] - r[e];
+}
+
+}  // namespace
+
+fe_status k_nodes(const Mesh& m, double* xyz, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(nodes_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.n1, (long long)m.nf, xyz, w);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_kdiag(const Mesh& m, double* d, hipStream_t s) {
+  hipLaunchKernelGGL(kdiag_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.n1, (long long)m.nf, d);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_dinv(const Mesh& m, double* dinv, hipStream_t s) {
+  hipLaunchKernelGGL(dinv_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.n1, (long long)m.nf, dinv);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_density(const Mesh& m, const double* Psi, int nocc, const double* occ_h, double* rho, hipStream_t s) {
+  Occ o{};
+  for (int i = 0; i < nocc; ++i) o.f[i] = occ_h[i];
+  hipLaunchKernelGGL(density_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, Psi, nocc, o, m.d_w1, m.n1,
+                     (long long)m.nf, rho);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+size_t loss_work_bytes() { return 1025 * sizeof(double); }
+
+fe_status k_loss(const Mesh& m, const double* rho, const double* rho_d, double* out, void* work, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((m.nf + 4095) / 4096, 1024));
+  const long long per = (m.nf + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  hipLaunchKernelGGL(loss_partial_kernel, dim3(nblk), dim3(256), 0, s, rho, rho_d, m.d_w1, m.n1, (long long)m.nf,
+                     per, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_serial_kernel, dim3(1), dim3(64), 0, s, partial, nblk, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_rhs(const Mesh& m, const double* Psi, int nocc, const double* occ_h, const double* rho,
+                const double* rho_d, double* R, hipStream_t s) {
+  Occ o{};
+  for (int i = 0; i < nocc; ++i) o.f[i] = occ_h[i];
+  hipLaunchKernelGGL(rhs_kernel, dim3(grid_for(m.nf * nocc)), dim3(256), 0, s, Psi, nocc, o, rho, rho_d,
+                     (long long)m.nf, R);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_grad(const Mesh& m, const double* Psi, const double* Q, int nocc, const double* rho_d, double tau,
+                 double* g, hipStream_t s) {
+  hipLaunchKernelGGL(grad_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, Psi, Q, nocc, rho_d, tau, (long long)m.nf, g);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// ----------------------------------------------------------------- MINRES
+int mr_state_count() { return S_COUNT; }
+int mr_state_iters() { return S_ITERS; }
+int mr_state_relres() { return S_RELRES; }
+int mr_state_active() { return S_ACTIVE; }
+int mr_state_invbeta() { return S_INVBETA; }
+
+fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
+  hipLaunchKernelGGL(mr_init_kernel<double>, dim3(1), dim3(256), 0, s, st, dot_r_z, k);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status mr_dots(const double* z, const double* y, const double* r1, int k, int64_t nf, double* d1, double* d2,
+                  double* partial, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 1023) / 1024, 1024));
+  const long long per = (nf + nblk - 1) / nblk;
+  double* p1 = partial;
+  double* p2 = partial + (size_t)nblk * k;
+  hipLaunchKernelGGL(mr_dots_kernel, dim3(nblk), dim3(256), 0, s, z, y, r1, k, (long long)nf, per, p1, p2);
+  INVDFT_HIP(hipGetLastError());
+  return sum_columns(p1, nblk, k, d1, s) == FE_OK ? sum_columns(p2, nblk, k, d2, s) : FE_EDEVICE;
+}
+
+size_t mr_dots_work_bytes(int64_t nf, int k) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 1023) / 1024, 1024));
+  return (size_t)2 * nblk * k * sizeof(double);
+}
+
+fe_status mr_alfa(double* st, const double* d1, const double* d2, int k, bool first, hipStream_t s) {
+  hipLaunchKernelGGL(mr_alfa_kernel, dim3(1), dim3(256), 0, s, st, d1, d2, k, first ? 1 : 0);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status mr_givens(double* st, const double* dot_r_z, int k, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(mr_givens_kernel, dim3(1), dim3(256), 0, s, st, dot_r_z, k, tol);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status mr_resid_precond(double* y, double* r1, const double* r2, const double* st, const double* dinv, int k,
+                           int64_t nf, hipStream_t s) {
+  hipLaunchKernelGGL(mr_resid_precond_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, y, r1, r2, st, dinv, k,
+                     (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status mr_update(const double* zold, double* w1, const double* w2, double* x, const double* st, int k, int64_t nf,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(mr_update_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, zold, w1, w2, x, st, k, (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_precond(const double* x, const double* dinv, int k, int64_t nf, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(precond_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, x, dinv, k, (long long)nf, y);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_sub_from(const double* b, double* r, int64_t total, hipStream_t s) {
+  hipLaunchKernelGGL(sub_from_kernel, dim3(grid_for(total)), dim3(256), 0, s, b, r, (long long)total);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+}  // namespace invdft
