@@ -1,0 +1,235 @@
+"""Benchmark of the inverse-DFT hot path on one MI355X.
+
+A step is one gradient iteration of the inverse loop: the forward Chebyshev-
+filtered eigensolve (warm-started from the previous iterate's orbitals), the
+density/loss/adjoint right-hand side, the batched MINRES adjoint solve, the
+gradient (all behind the autograd Function), and the potential update. Two
+paths run the same steps: the plain FP64 GPU path and the mixed-precision path
+(FP32 filter and FP32 MINRES with FP64 refinement, orbitals recomputed in
+backward). `value` is the mixed path's gradient iterations per second.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def apply_timing(api, mesh, v, nv, prec, reps=20):
+    """Average ks_apply duration (ms) from HIP events on the launch stream."""
+    import torch
+    dt = torch.float64 if prec == "f64" else torch.float32
+    X = torch.randn(mesh.n_free, nv, device=v.device, dtype=dt)
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        api.ks_apply(mesh, v, X, Y, prec=prec)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        api.ks_apply(mesh, v, X, Y, prec=prec)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    s = 8 if prec == "f64" else 4
+    algo_bytes = 2 * mesh.n_free * nv * s + mesh.n_free * 8
+    del X, Y
+    return ms, algo_bytes
+
+
+def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, step_len):
+    import torch
+    prob = inv.InverseProblem(mesh, v_fixed, rho_d, n_elec, X0, opts)
+    u = torch.zeros_like(v_fixed)
+    losses, grads = [], []
+
+    def one_step(u):
+        ur = u.detach().clone().requires_grad_(True)
+        loss = inv.InvDFTLoss.apply(ur, prob)
+        loss.backward()
+        g = ur.grad.detach()
+        gmax = float(g.abs().max())          # scalar read-back for the step length only
+        if gmax > 0:
+            api.axpby(-step_len / gmax, g, 1.0, u)
+        return float(loss.detach()), g
+
+    for w in range(warmup):
+        l, g = one_step(u)
+        log(f"  warmup {w}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
+    prob.stats = inv.Stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        l, g = one_step(u)
+        losses.append(l)
+        grads.append(g.clone() if k == 0 else None)
+        log(f"  step {k}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, losses, grads[0], prob
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="f64,mixed")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only time ks_apply on the workload mesh (used for kernel profiles)")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_10529_amd import api
+    from paper_2510_10529_amd import inverse as inv
+    from synth import random_block, workload
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    wl = workload(args.config)
+    log(f"workload {wl.name}: p={wl.p} n={wl.n} L={wl.half_width} N_e={wl.n_elec}")
+    mesh = api.Mesh(wl.p, wl.n, wl.half_width)
+    xyz, W = mesh.nodes()
+    xyz_h = xyz.cpu().numpy()
+    del xyz
+    v_fixed = torch.tensor(wl.v_fixed(xyz_h), device=dev)
+    v_star = torch.tensor(wl.v_xc_target(xyz_h), device=dev)
+    del xyz_h
+    nocc, nv = wl.n_occ, wl.n_occ + wl.n_buf
+    log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}")
+    if args.apply_only:
+        out = {}
+        for prec, cols in (("f64", nocc), ("f32", nv)):
+            ms, b = apply_timing(api, mesh, v_fixed, cols, prec, reps=args.reps)
+            out[f"ks_apply_{prec}"] = {"columns": cols, "ms": ms, "algorithmic_bytes": b,
+                                       "GBps": b / ms / 1e6, "hbm_frac": b / ms / 1e6 / HBM_PEAK_GBS}
+            log(f"ks_apply {prec} nv={cols}: {ms:.3f} ms, {b / ms / 1e6:.0f} GB/s")
+        print(json.dumps({"workload": wl.name, "n_free": mesh.n_free, **out}), flush=True)
+        return
+    X0 = torch.tensor(random_block(mesh.n_free, nv, 1000 + args.config), device=dev)
+
+    # target density rho_data = rho(v_fixed + v*) (untimed set-up)
+    t0 = time.perf_counter()
+    v_t = v_fixed + v_star
+    Xt = X0.clone()
+    r = api.ks_eigensolve(mesh, v_t, Xt, nocc, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+    rho_d, _, _ = api.loss_grad(mesh, Xt[:, :nocc].contiguous(), [2.0] * nocc, torch.zeros_like(v_t), want_B=False)
+    del Xt, v_t
+    # warm start for the inverse loop: orbitals of v_fixed (u = 0)
+    Xw = X0.clone()
+    api.ks_eigensolve(mesh, v_fixed, Xw, nocc, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+    torch.cuda.synchronize()
+    log(f"set-up (target density + initial orbitals) {time.perf_counter() - t0:.1f} s, target passes {r.passes}")
+    del X0
+
+    step_len = 0.01
+    results = {}
+    common = dict(degree=wl.cheb_degree, tol_eig=1e-9, tol_adj=1e-10, maxpass=100, maxit_adj=20000)
+    paths = {
+        "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
+        "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f32", switch_tol=1e-4,
+                                   recompute=True),
+    }
+    for name in args.paths.split(","):
+        log(f"path {name}")
+        el, losses, g0, prob = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name], args.steps,
+                                        args.warmup, step_len)
+        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats)
+        log(f"path {name}: {args.steps / el:.4f} iters/s  forward {prob.stats.t_forward:.2f} s  "
+            f"adjoint {prob.stats.t_adjoint:.2f} s")
+        del prob
+
+    head = results.get("mixed") or results["f64"]
+    ips = args.steps / head["elapsed"]
+    out_extra = {}
+    if "mixed" in results and "f64" in results:
+        g64, gm = results["f64"]["g0"], results["mixed"]["g0"]
+        rel = float(torch.linalg.vector_norm(gm - g64) / torch.linalg.vector_norm(g64))
+        ips64 = args.steps / results["f64"]["elapsed"]
+        out_extra = {"fp64_path_iters_per_s": ips64, "speedup_vs_fp64_path": ips / ips64,
+                     "grad_rel_diff_mixed_vs_fp64": rel}
+
+    # roofline of the dominant kernel (ks_apply) with HIP events on the launch stream
+    ms32, b32 = apply_timing(api, mesh, v_fixed, nv, "f32")
+    ms64, b64 = apply_timing(api, mesh, v_fixed, nocc, "f64")
+    gbs32 = b32 / ms32 / 1e6
+    gbs64 = b64 / ms64 / 1e6
+    log(f"ks_apply f32 nv={nv}: {ms32:.3f} ms {gbs32:.0f} GB/s ; f64 nv={nocc}: {ms64:.3f} ms {gbs64:.0f} GB/s")
+
+    st = head["stats"]
+    applies = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import fe as ofe
+        log("cpu baseline: one oracle Kronecker apply of the occupied block on the full mesh")
+        om = ofe.mesh3d(wl.p, wl.n, wl.half_width)
+        rng = np.random.default_rng(5)
+        Xc = rng.standard_normal((om.n_free, nocc))
+        vc = v_fixed.cpu().numpy()
+        t0 = time.perf_counter()
+        ofe.hamiltonian_apply(om, vc, Xc)
+        t_apply = time.perf_counter() - t0
+        del Xc
+        # applies per gradient iteration of the measured GPU path: filter passes x degree + MINRES iterations
+        passes = sum(st.passes) / max(1, len(st.passes)) * (st.n_forward / max(1, args.steps))
+        applies = passes * (wl.cheb_degree + 1) + sum(st.adj_iters) / max(1, len(st.adj_iters)) + 2
+        cpu = {"value": 1.0 / (t_apply * applies), "unit": "grad_iter/s", "cores": os.cpu_count(),
+               "kind": "oracle",
+               "sample": (f"one FP64 oracle Kronecker apply of the {nocc}-column block on the {om.n_free}-node "
+                          f"mesh ({t_apply:.1f} s), scaled by {applies:.0f} applies per gradient iteration "
+                          f"(the GPU path's measured filter passes x degree + MINRES iterations)")}
+
+    line = {
+        "metric": "ks_apply GB/s (% roofline) + inverse-DFT gradient iters/s vs FP64 GPU path",
+        "value": ips,
+        "unit": "grad_iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * head["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if "mixed" in results else "f64",
+        "data": "synthetic (seeded model molecule; target density from a known potential)",
+        "config": {"workload": wl.name, "p": wl.p, "cells_per_dim": wl.n, "half_width": wl.half_width,
+                   "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree},
+        "ks_apply_GBps_f32": gbs32,
+        "ks_apply_GBps_f64": gbs64,
+        "ks_apply_ms_f32": ms32,
+        "ks_apply_ms_f64": ms64,
+        **out_extra,
+        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None},
+        "roofline_f64": {"bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs64 / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

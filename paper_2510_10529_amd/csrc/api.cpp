@@ -226,19 +226,25 @@ EigWork eig_layout(Bump& bp, const Mesh& m, int nv, int ld, fe_prec prec) {
 }
 
 // ------------------------------------------------------------------ MINRES
+// Work blocks of one MINRES solve in storage type T (FP64 or FP32).
 struct MRWork {
-  double *R1, *R2, *Z, *Y, *Wa, *Wb, *dinv, *st, *d1, *d2, *bnorm, *dots, *pw, *qcopy;
+  void *R1, *R2, *Z, *Y, *Wa, *Wb, *X;   // X: the solution of the inner solve (FP32 path only)
+  double *dinv, *st, *d1, *d2, *bnorm, *dots, *pw;
+  // FP32 refinement extras
+  float* Psif;    // FP32 copy of Psi
+  double *R64, *Y64;
 };
 
-MRWork mr_layout(Bump& bp, const Mesh& m, int k) {
+MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
   MRWork w{};
   const size_t blk = (size_t)m.nf * k;
-  w.R1 = bp.take<double>(blk);
-  w.R2 = bp.take<double>(blk);
-  w.Z = bp.take<double>(blk);
-  w.Y = bp.take<double>(blk);
-  w.Wa = bp.take<double>(blk);
-  w.Wb = bp.take<double>(blk);
+  const size_t es = prec == FE_F64 ? sizeof(double) : sizeof(float);
+  w.R1 = bp.take<char>(blk * es);
+  w.R2 = bp.take<char>(blk * es);
+  w.Z = bp.take<char>(blk * es);
+  w.Y = bp.take<char>(blk * es);
+  w.Wa = bp.take<char>(blk * es);
+  w.Wb = bp.take<char>(blk * es);
   w.dinv = bp.take<double>(m.nf);
   w.st = bp.take<double>((size_t)mr_state_count() * k);
   w.d1 = bp.take<double>(k);
@@ -246,93 +252,109 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k) {
   w.bnorm = bp.take<double>(k);
   w.dots = bp.take<double>(mr_dots_work_bytes(m.nf, k) / sizeof(double) + 1);
   w.pw = bp.take<double>(std::max(project_work_bytes(m.nf, k, k), coldot_work_bytes(m.nf, k)) / sizeof(double) + 1);
+  if (prec != FE_F64) {
+    w.X = bp.take<char>(blk * es);
+    w.Psif = bp.take<float>(blk);
+    w.R64 = bp.take<double>(blk);
+    w.Y64 = bp.take<double>(blk);
+  }
   return w;
 }
 
-// One FP64 MINRES solve of P (H - eps_i) P q_i = b_i, q_i in the complement of Psi.
-fe_status minres_f64(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k, const double* B,
-                     double* Q, double tol, int maxit, MRWork& w, int* iters_h, double* relres_h, bool* converged,
-                     hipStream_t s) {
+template <typename T>
+fe_status fill_t(T* y, int64_t n, hipStream_t s);
+template <>
+fe_status fill_t<double>(double* y, int64_t n, hipStream_t s) { return fill(y, 0.0, n, s); }
+template <>
+fe_status fill_t<float>(float* y, int64_t n, hipStream_t s) { return fill_f32(y, 0.0f, n, s); }
+
+// MINRES (Paige and Saunders 1975) on P (H - eps_i) P q_i = b_i for all columns in lockstep,
+// preconditioner P D^{-1} P. Blocks of type T; every per-column scalar in FP64 on the device.
+// On return `iters` holds per-column iteration counts, `active` the still-unconverged flags.
+template <typename T>
+fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double* eps_h, int k, const T* B, T* Q,
+                      double tol, int maxit, MRWork& w, std::vector<double>& iters, std::vector<double>& active,
+                      hipStream_t s) {
   const int64_t nf = m.nf;
   const size_t blk = (size_t)nf * k;
+  const bool f32 = sizeof(T) == sizeof(float);
+  const fe_prec prec = f32 ? FE_F32 : FE_F64;
   fe_status st;
-  if ((st = fill(Q, 0.0, blk, s)) != FE_OK) return st;
-  if ((st = fill(w.Wa, 0.0, blk, s)) != FE_OK) return st;
-  if ((st = fill(w.Wb, 0.0, blk, s)) != FE_OK) return st;
-  if ((st = copy_block(B, w.R1, blk, s)) != FE_OK) return st;
-  if ((st = copy_block(B, w.R2, blk, s)) != FE_OK) return st;
-  if ((st = k_dinv(m, w.dinv, s)) != FE_OK) return st;
+  if ((st = fill_t<T>(Q, blk, s)) != FE_OK) return st;
+  if ((st = fill_t<T>(static_cast<T*>(w.Wa), blk, s)) != FE_OK) return st;
+  if ((st = fill_t<T>(static_cast<T*>(w.Wb), blk, s)) != FE_OK) return st;
+  if ((st = copy_bytes(B, w.R1, blk * sizeof(T), s)) != FE_OK) return st;
+  if ((st = copy_bytes(B, w.R2, blk * sizeof(T), s)) != FE_OK) return st;
   // z = P D^{-1} b ; beta1 = sqrt(b.z)
-  if ((st = k_precond(B, w.dinv, k, nf, w.Z, s)) != FE_OK) return st;
-  if ((st = project_out(Psi, k, w.Z, k, nf, false, w.pw, s)) != FE_OK) return st;
-  if ((st = coldot(w.R1, w.Z, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = k_precond<T>(B, w.dinv, k, nf, static_cast<T*>(w.Z), s)) != FE_OK) return st;
+  if ((st = project_out(Psi, k, w.Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
+  if ((st = coldot(w.R1, w.Z, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
   if ((st = mr_init(w.st, w.d1, k, s)) != FE_OK) return st;
-  double *R1 = w.R1, *R2 = w.R2, *Z = w.Z, *Y = w.Y, *Wa = w.Wa, *Wb = w.Wb;
+  T *R1 = static_cast<T*>(w.R1), *R2 = static_cast<T*>(w.R2), *Z = static_cast<T*>(w.Z), *Y = static_cast<T*>(w.Y);
+  T *Wa = static_cast<T*>(w.Wa), *Wb = static_cast<T*>(w.Wb);
   ApplyArgs aa{};
   aa.v = v;
   aa.nv = k;
   aa.ld = k;
   aa.alpha = 1.0;
   aa.colshift = eps_h;
-  std::vector<double> active(k);
-  int it = 0;
-  bool all_done = false;
+  active.assign(k, 1.0);
   const int check_every = 8;
-  for (it = 1; it <= maxit; ++it) {
+  for (int it = 1; it <= maxit; ++it) {
     // y = P (H - eps) (z / beta)
     aa.X = Z;
     aa.Y = Y;
     aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
-    if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
-    if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
+    if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
     // alfa = v.(y - c1 r1)
-    if ((st = mr_dots(Z, Y, R1, k, nf, w.d1, w.d2, w.dots, s)) != FE_OK) return st;
+    if ((st = mr_dots<T>(Z, Y, R1, k, nf, w.d1, w.d2, w.dots, s)) != FE_OK) return st;
     if ((st = mr_alfa(w.st, w.d1, w.d2, k, it == 1, s)) != FE_OK) return st;
     // r_new = y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; u <- P u
-    if ((st = mr_resid_precond(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
+    if ((st = mr_resid_precond<T>(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
-    if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
-    if ((st = coldot(R2, Y, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
+    if ((st = coldot(R2, Y, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
     if ((st = mr_givens(w.st, w.d1, k, tol, s)) != FE_OK) return st;
-    if ((st = mr_update(Z, Wb, Wa, Q, w.st, k, nf, s)) != FE_OK) return st;
+    if ((st = mr_update<T>(Z, Wb, Wa, Q, w.st, k, nf, s)) != FE_OK) return st;
     std::swap(Wa, Wb);
     std::swap(Z, Y);
     if (it % check_every == 0 || it == maxit) {
       INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
       INVDFT_HIP(hipStreamSynchronize(s));
-      all_done = true;
+      bool done = true;
       for (int j = 0; j < k; ++j)
-        if (active[j] > 0.0) all_done = false;
-      if (all_done) break;
+        if (active[j] > 0.0) done = false;
+      if (done) break;
     }
   }
-  // final projection (round-off only) and the true residual ||b - P(H - eps)q|| / ||b||
-  if ((st = project_out(Psi, k, Q, k, nf, false, w.pw, s)) != FE_OK) return st;
-  aa.X = Q;
-  aa.Y = Y;
-  aa.d_colscale = nullptr;
-  if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
-  if ((st = project_out(Psi, k, Y, k, nf, false, w.pw, s)) != FE_OK) return st;
-  if ((st = k_sub_from(B, Y, blk, s)) != FE_OK) return st;
-  if ((st = coldot(Y, Y, k, nf, k, false, w.d1, w.pw, s)) != FE_OK) return st;
-  if ((st = coldot(B, B, k, nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
-  std::vector<double> rr(k), bb(k), its(k);
-  INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
-  INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
-  INVDFT_HIP(hipMemcpyAsync(its.data(), w.st + (size_t)mr_state_iters() * k, k * sizeof(double),
+  if ((st = project_out(Psi, k, Q, k, nf, f32, w.pw, s)) != FE_OK) return st;
+  iters.resize(k);
+  INVDFT_HIP(hipMemcpyAsync(iters.data(), w.st + (size_t)mr_state_iters() * k, k * sizeof(double),
                             hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
                             hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipStreamSynchronize(s));
-  bool ok = true;
-  for (int j = 0; j < k; ++j) {
-    if (iters_h) iters_h[j] = (int)its[j];
-    if (relres_h) relres_h[j] = bb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / bb[j]) : 0.0;
-    if (active[j] > 0.0) ok = false;
-  }
-  *converged = ok;
   return FE_OK;
+}
+
+// FP64 true residual R = B - P (H - eps) P Q and its column norms rr (device).
+fe_status true_residual(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k,
+                        const double* B, const double* Q, double* R, double* rr, double* pw, hipStream_t s) {
+  ApplyArgs aa{};
+  aa.v = v;
+  aa.nv = k;
+  aa.ld = k;
+  aa.alpha = 1.0;
+  aa.colshift = eps_h;
+  aa.X = Q;
+  aa.Y = R;
+  fe_status st;
+  if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, k, R, k, m.nf, false, pw, s)) != FE_OK) return st;
+  if ((st = k_sub_from(B, R, (int64_t)m.nf * k, s)) != FE_OK) return st;
+  return coldot(R, R, k, m.nf, k, false, rr, pw, s);
 }
 
 }  // namespace
@@ -492,7 +514,7 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
     case FE_OP_CHEB_FILTER: return filter_work(m, nv, prec);
     case FE_OP_RAYLEIGH_RITZ: rr_layout(bp, m, nv, nv); return bp.off;
     case FE_OP_EIGENSOLVE: eig_layout(bp, m, nv, nv, prec); return bp.off;
-    case FE_OP_ADJOINT_SOLVE: mr_layout(bp, m, nv); return bp.off;
+    case FE_OP_ADJOINT_SOLVE: mr_layout(bp, m, nv, prec); return bp.off;
     case FE_OP_LOSS_GRAD:
       bp.take<double>(m.nf);
       bp.take<double>(1025);
@@ -566,6 +588,10 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
   if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
   int pass = 0;
   bool conv = false;
+  // reduced-precision filter passes until the residual is below switch_tol or stops
+  // improving (its rounding floor), then FP64 passes
+  bool low = prec != FE_F64;
+  double rprev = 1e300;
   for (;;) {
     double rmax = 0.0;
     for (int i = 0; i < nocc; ++i) rmax = std::max(rmax, resnorm_h[i]);
@@ -576,7 +602,9 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     if (pass >= maxpass) break;
     const double a = eig_h[nv - 1], a0 = eig_h[0];
     if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "ks_eigensolve: degenerate filter interval");
-    if (prec != FE_F64 && rmax > switch_tol) {
+    if (low && (rmax <= switch_tol || rmax > 0.5 * rprev)) low = false;
+    rprev = rmax;
+    if (low) {
       if ((st = cast_block_to_f32(X, w.Xf, (int64_t)m.nf * ld, s)) != FE_OK) return st;
       if ((st = filter_impl(m, v, degree, a, b, a0, w.Xf, nv, ld, FE_F32, w.filt, s)) != FE_OK) return st;
       if ((st = cast_block_to_f64(w.Xf, X, (int64_t)m.nf * ld, s)) != FE_OK) return st;
@@ -645,14 +673,82 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
   if (!v || !Psi || !eps_h || !B || !Q || !work) return fail(FE_EINVAL, "adjoint_solve: NULL argument");
   if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "adjoint_solve: nocc must be in [1, 64]");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve: tol > 0 and maxit >= 1 required");
-  if (prec != FE_F64) return fail(FE_EINVAL, "adjoint_solve: unsupported precision");
+  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "adjoint_solve: unsupported precision");
   const Mesh& m = mesh->m;
   hipStream_t s = S(stream);
   Bump bp(work);
-  MRWork w = mr_layout(bp, m, nocc);
-  bool conv = false;
-  fe_status st = minres_f64(m, v, Psi, eps_h, nocc, B, Q, tol, maxit, w, iters_h, relres_h, &conv, s);
-  if (st != FE_OK) return st;
+  MRWork w = mr_layout(bp, m, nocc, prec);
+  const int k = nocc;
+  const size_t blk = (size_t)m.nf * k;
+  fe_status st;
+  if ((st = k_dinv(m, w.dinv, s)) != FE_OK) return st;
+  std::vector<double> its, active, total_its(k, 0.0), rr(k), bb(k);
+  bool conv = true;
+  if (prec == FE_F64) {
+    if ((st = minres_core<double>(m, v, Psi, eps_h, k, B, Q, tol, maxit, w, its, active, s)) != FE_OK) return st;
+    total_its = its;
+    for (int j = 0; j < k; ++j)
+      if (active[j] > 0.0) conv = false;
+    if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, static_cast<double*>(w.Y), w.d1, w.pw, s)) != FE_OK) return st;
+  } else {
+    // FP32 MINRES inner solves with FP64 iterative refinement: q += d, (H - eps) d = r in FP32,
+    // r = b - (H - eps) q in FP64, until every column reaches tol.
+    const double tol_inner = std::max(tol, 1e-4);
+    if ((st = cast_block_to_f32(Psi, w.Psif, blk, s)) != FE_OK) return st;
+    if ((st = fill(Q, 0.0, blk, s)) != FE_OK) return st;
+    if ((st = copy_bytes(B, w.R64, blk * sizeof(double), s)) != FE_OK) return st;
+    if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
+    INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    if ((st = copy_bytes(w.bnorm, w.d1, k * sizeof(double), s)) != FE_OK) return st;  // r = b at q = 0
+    INVDFT_HIP(hipStreamSynchronize(s));
+    rr = bb;
+    int used = 0;
+    const int max_outer = 20;
+    conv = false;
+    for (int outer = 0; outer < max_outer && used < maxit; ++outer) {
+      bool done = true;
+      for (int j = 0; j < k; ++j)
+        if (rr[j] > tol * tol * bb[j]) done = false;
+      if (done) {
+        conv = true;
+        break;
+      }
+      float* Rf = static_cast<float*>(w.X);  // right-hand side of the inner solve
+      if ((st = cast_block_to_f32(w.R64, Rf, blk, s)) != FE_OK) return st;
+      if ((st = k_mask_cols(Rf, w.d1, w.bnorm, tol, k, m.nf, s)) != FE_OK) return st;
+      // the FP32 correction is stored in the (larger) FP64 scratch block Y64
+      float* Dsol = reinterpret_cast<float*>(w.Y64);
+      if ((st = minres_core<float>(m, v, w.Psif, eps_h, k, Rf, Dsol, tol_inner, maxit - used, w, its, active, s)) !=
+          FE_OK)
+        return st;
+      int mx = 0;
+      for (int j = 0; j < k; ++j) {
+        total_its[j] += its[j];
+        mx = std::max(mx, (int)its[j]);
+      }
+      used += std::max(mx, 1);
+      if ((st = k_add_f32(Dsol, Q, blk, s)) != FE_OK) return st;
+      if ((st = project_out(Psi, k, Q, k, m.nf, false, w.pw, s)) != FE_OK) return st;
+      if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.R64, w.d1, w.pw, s)) != FE_OK) return st;
+      INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
+      INVDFT_HIP(hipStreamSynchronize(s));
+    }
+    if (!conv) {
+      bool done = true;
+      for (int j = 0; j < k; ++j)
+        if (rr[j] > tol * tol * bb[j]) done = false;
+      conv = done;
+    }
+    if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
+  }
+  if (prec == FE_F64 && (st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    if (iters_h) iters_h[j] = (int)total_its[j];
+    if (relres_h) relres_h[j] = bb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / bb[j]) : 0.0;
+  }
   if (!conv) return fail(FE_ENOCONV, "adjoint_solve: some columns did not converge in maxit iterations");
   return FE_OK;
 }

@@ -49,9 +49,19 @@ struct KParams {
   double colshift[kMaxShiftCols];
 };
 
+// Tile shape per order: BEX x BEY cells per workgroup in x and y (a z-range of
+// cells is marched). Small tiles keep LDS near 24 KB and registers near 110, so
+// about four workgroups share a CU and overlap each other's barriers and loads.
+#ifndef KS_APPLY_MIN_WAVES
+#define KS_APPLY_MIN_WAVES 1
+#endif
+#ifndef KS_APPLY_BEY5
+#define KS_APPLY_BEY5 1
+#endif
 template <int P>
 struct TileShape {
-  static constexpr int BE = (P <= 2) ? 4 : ((P <= 5) ? 2 : 1);  // cells per tile edge
+  static constexpr int BEX = (P == 1) ? 4 : (P == 2) ? 4 : (P <= 5) ? 2 : 1;
+  static constexpr int BEY = (P == 1) ? 4 : (P == 2) ? 2 : (P <= 4) ? 2 : (P == 5) ? KS_APPLY_BEY5 : 1;
 };
 
 // The scaled 1-D element matrices are symmetric and centrosymmetric
@@ -80,23 +90,33 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
 }
 
 template <typename T, int P, int J, int NT>
-__global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
+__global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const KParams prm) {
   using CT = T;  // compute type = storage type (FP64 or FP32)
   constexpr int P1 = P + 1;
-  constexpr int BE = TileShape<P>::BE;
-  constexpr int BX = BE * P;              // owned nodes per tile edge
-  constexpr int NYI = (BE + 1) * P + 1;   // rows of the x-pass (owned + halo)
-  constexpr int NXI = BE * NYI * J;       // x-pass items
-  constexpr int XPT = (NXI + NT - 1) / NT;
-  constexpr int NYP = BX * BE * J;        // y-pass items
-  constexpr int NCOL = BX * BX * J;       // owned (x, y, column) z-columns
+  constexpr int BEX = TileShape<P>::BEX, BEY = TileShape<P>::BEY;
+  constexpr int BX = BEX * P, BY = BEY * P;  // owned nodes per tile edge
+  constexpr int NYI = (BEY + 1) * P + 1;     // input rows (owned + halo)
+  constexpr int NXN = (BEX + 1) * P + 1;     // input nodes per row (owned + halo)
+  constexpr int NXI = BEX * NYI * J;         // x-pass items
+  constexpr int NYP = BX * BEY * J;          // y-pass items
+  constexpr int NCOL = BX * BY * J;          // owned (x, y, column) z-columns
   constexpr int CPT = (NCOL + NT - 1) / NT;
+  constexpr int EPC = 16 / sizeof(T);        // elements per 16-byte chunk
+  constexpr int CPN = J / EPC;               // chunks per node
+  constexpr int NCHUNK = NYI * NXN * CPN;    // 16-byte chunks of one input plane
+  constexpr int LPT = (NCHUNK + NT - 1) / NT;
+  constexpr int NVO = BX * BY;               // owned nodes (potential values)
+  constexpr int VPT = (NVO + NT - 1) / NT;
+  static_assert(J % EPC == 0, "column chunk must be a whole number of 16-byte pieces");
 
-  __shared__ CT sU1[2][NYI][BX][J];
-  __shared__ CT sU2[2][NYI][BX][J];
-  __shared__ CT sD[2][BX][BX][J];         // diagonal term (v - c - s_j) x of the plane
-  __shared__ CT sA[BX][BX][J];
-  __shared__ CT sB[BX][BX][J];
+  typedef T T16 __attribute__((ext_vector_type(EPC)));
+  __shared__ __attribute__((aligned(16))) CT sIn[NYI][NXN][J];  // raw input plane
+  __shared__ CT sU1[NYI][BX][J];
+  __shared__ CT sU2[NYI][BX][J];
+  __shared__ CT sA[BY][BX][J];
+  __shared__ CT sB[BY][BX][J];
+  __shared__ CT sD[2][BY][BX][J];            // diagonal term (v - c - s_j) x, double-buffered
+  __shared__ double sV[BY][BX];              // potential at the owned nodes of the plane
 
   const T* __restrict__ X = static_cast<const T*>(prm.X);
   T* Y = static_cast<T*>(prm.Y);  // may alias Z, never X
@@ -112,10 +132,12 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   bid /= prm.tiles_x;
   const int ty = bid % prm.tiles_y;
   const int zs = bid / prm.tiles_y;
-  const int ex0 = tx * BE, ey0 = ty * BE, j0 = jc * J;
+  const int ex0 = tx * BEX, ey0 = ty * BEY, j0 = jc * J;
   const int ez0 = zs * prm.zseg;
   const int ez1 = min(n, ez0 + prm.zseg);
   const int ezs = (ez0 > 0) ? ez0 - 1 : 0;
+  // 16-byte vector loads need the chunk start aligned: ld a multiple of EPC (j0 is)
+  const bool vec_ok = (ld % EPC) == 0;
 
   auto node_ok = [&](int g) { return g >= 1 && g <= pn - 1; };
   auto node_index = [&](int gx, int gy, int gz) -> long long {
@@ -124,35 +146,61 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   auto MT = [&](int i, int k) { return (CT)prm.mt[canon_index(i, k, P)]; };
   auto KT = [&](int i, int k) { return (CT)prm.kt[canon_index(i, k, P)]; };
 
-  // ---------------------------------------------------------------- x-item inputs
-  // x-item (jj, exl, yl): the 2P+1 nodes gx = ex P - P .. ex P + P of row gy, column j.
-  CT cur[XPT][2 * P + 1], nxt[XPT][2 * P + 1];
-  double vcur[XPT][P], vnxt[XPT][P];
-  auto load_items = [&](int gz, CT (*in)[2 * P + 1], double (*vv)[P]) {
+  // ---- plane loader: non-redundant 16-byte chunks into registers (prefetch), then LDS
+  T16 pre[LPT];
+  double vpre[VPT];
+  auto load_plane = [&](int gz) {
     const bool zok = node_ok(gz);
 #pragma unroll
-    for (int t = 0; t < XPT; ++t) {
-      const int item = tid + t * NT;
-      const int jj = item % J;
-      const int r = item / J;
-      const int exl = r % BE;
-      const int yl = r / BE;
-      const int gy = (ey0 - 1) * P + yl;
-      const int ex = ex0 + exl;
-      const int j = j0 + jj;
-      const bool rowok = item < NXI && zok && node_ok(gy) && j < nv;
-      const long long rowbase = rowok ? node_index(1, gy, gz) : 0;
+    for (int t = 0; t < LPT; ++t) {
+      const int c = tid + t * NT;
+      T16 val;
 #pragma unroll
-      for (int k = 0; k <= 2 * P; ++k) {
-        const int gx = ex * P - P + k;
-        in[t][k] = (rowok && node_ok(gx)) ? X[(rowbase + gx - 1) * ld + j] : CT(0);
-      }
-      const bool own = rowok && yl >= P && yl < P + BX;
+      for (int e = 0; e < EPC; ++e) val[e] = T(0);
+      if (c < NCHUNK && zok) {
+        const int part = c % CPN;
+        const int r = c / CPN;
+        const int xn = r % NXN;
+        const int yl = r / NXN;
+        const int gx = ex0 * P - P + xn, gy = ey0 * P - P + yl;
+        const int jb = j0 + part * EPC;
+        if (node_ok(gx) && node_ok(gy) && jb < nv) {
+          const T* src = X + node_index(gx, gy, gz) * ld + jb;
+          if (vec_ok && jb + EPC <= nv) {
+            val = *reinterpret_cast<const T16*>(src);
+          } else {
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const int gx = ex * P + i;
-        vv[t][i] = (own && node_ok(gx)) ? prm.v[rowbase + gx - 1] : 0.0;
+            for (int e = 0; e < EPC; ++e) val[e] = (jb + e < nv) ? src[e] : T(0);
+          }
+        }
       }
+      pre[t] = val;
+    }
+#pragma unroll
+    for (int t = 0; t < VPT; ++t) {
+      const int o = tid + t * NT;
+      double vv = 0.0;
+      if (o < NVO && zok) {
+        const int gx = ex0 * P + o % BX, gy = ey0 * P + o / BX;
+        if (node_ok(gx) && node_ok(gy)) vv = prm.v[node_index(gx, gy, gz)];
+      }
+      vpre[t] = vv;
+    }
+  };
+  auto store_plane = [&]() {
+#pragma unroll
+    for (int t = 0; t < LPT; ++t) {
+      const int c = tid + t * NT;
+      if (c < NCHUNK) {
+        const int part = c % CPN;
+        const int r = c / CPN;
+        *reinterpret_cast<T16*>(&sIn[r / NXN][r % NXN][part * EPC]) = pre[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < VPT; ++t) {
+      const int o = tid + t * NT;
+      if (o < NVO) sV[o / BX][o % BX] = vpre[t];
     }
   };
 
@@ -164,47 +212,49 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
     for (int i = 0; i <= P; ++i) acc[c][i] = 0;
 
   const int gz0 = ezs * P, gz1 = ez1 * P;
-  load_items(gz0, cur, vcur);
+  load_plane(gz0);
+  store_plane();
+  __syncthreads();
   int buf = 0;
   const CT half = CT(0.5);
 #pragma unroll 1
   for (int gz = gz0; gz <= gz1; ++gz) {
-    if (gz < gz1) load_items(gz + 1, nxt, vnxt);  // prefetch: in flight during this plane
-    // ---- x-pass: U1 = M~x X, U2 = K~x X on owned x, all NYI rows; diagonal term on owned rows
-#pragma unroll
-    for (int t = 0; t < XPT; ++t) {
-      const int item = tid + t * NT;
-      if (item >= NXI) continue;
+    if (gz < gz1) load_plane(gz + 1);  // prefetch: in flight during this plane's passes
+    // ---- x-pass (LDS -> LDS): U1 = M~x X, U2 = K~x X on owned x, all NYI rows; diagonal term
+    for (int item = tid; item < NXI; item += NT) {
       const int jj = item % J;
       const int r = item / J;
-      const int exl = r % BE;
-      const int yl = r / BE;
+      const int exl = r % BEX;
+      const int yl = r / BEX;
+      CT in[2 * P + 1];
+#pragma unroll
+      for (int k = 0; k <= 2 * P; ++k) in[k] = sIn[yl][exl * P + k][jj];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         CT u1 = 0, u2 = 0;
 #pragma unroll
         for (int k = 0; k <= P; ++k) {
-          u1 += MT(i, k) * cur[t][P + k];
-          u2 += KT(i, k) * cur[t][P + k];
+          u1 += MT(i, k) * in[P + k];
+          u2 += KT(i, k) * in[P + k];
         }
-        if (i == 0) {
+        if (i == 0) {  // shared vertex: the left cell's row P as well
 #pragma unroll
-          for (int k = 0; k < P; ++k) {  // left cell's row P (its node P is cur[t][P], already counted)
-            u1 += MT(P, k) * cur[t][k];
-            u2 += KT(P, k) * cur[t][k];
+          for (int k = 0; k < P; ++k) {
+            u1 += MT(P, k) * in[k];
+            u2 += KT(P, k) * in[k];
           }
-          u1 += MT(P, P) * cur[t][P];
-          u2 += KT(P, P) * cur[t][P];
+          u1 += MT(P, P) * in[P];
+          u2 += KT(P, P) * in[P];
         }
-        sU1[buf][yl][exl * P + i][jj] = u1;
-        sU2[buf][yl][exl * P + i][jj] = u2;
+        sU1[yl][exl * P + i][jj] = u1;
+        sU2[yl][exl * P + i][jj] = u2;
       }
-      if (yl >= P && yl < P + BX) {
+      if (yl >= P && yl < P + BY) {
         const int j = j0 + jj;
         const double sh = prm.cshift + ((prm.has_colshift && j < nv) ? prm.colshift[j] : 0.0);
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          sD[buf][yl - P][exl * P + i][jj] = (CT)((vcur[t][i] - sh) * (double)cur[t][P + i]);
+          sD[buf][yl - P][exl * P + i][jj] = (CT)((sV[yl - P][exl * P + i] - sh) * (double)in[P + i]);
       }
     }
     __syncthreads();
@@ -217,8 +267,8 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       CT a1[2 * P + 1], a2[2 * P + 1];
 #pragma unroll
       for (int k = 0; k <= 2 * P; ++k) {
-        a1[k] = sU1[buf][eyl * P + k][xl][jj];
-        a2[k] = sU2[buf][eyl * P + k][xl][jj];
+        a1[k] = sU1[eyl * P + k][xl][jj];
+        a2[k] = sU2[eyl * P + k][xl][jj];
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) {
@@ -239,6 +289,8 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
         sB[eyl * P + i][xl][jj] = B;
       }
     }
+    // the raw plane and potential were last read by this plane's x-pass (before the barrier above)
+    if (gz < gz1) store_plane();
     __syncthreads();
     // ---- z-step: plane gz is node k of the current cell (k = 0 only for the first plane)
     const int rel = gz - gz0;
@@ -249,19 +301,23 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       mcol[i] = half * (CT)prm.mt[canon_index(i, k, P)];
       kcol[i] = half * (CT)prm.kt[canon_index(i, k, P)];
     }
+    CT av[CPT], bv[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int col = tid + c * NT;
+      av[c] = bv[c] = 0;
       if (col >= NCOL) continue;
       const int jj = col % J;
       const int xl = (col / J) % BX;
       const int yl = col / (J * BX);
       const CT a = sA[yl][xl][jj], b = sB[yl][xl][jj], d = sD[buf][yl][xl][jj];
+      av[c] = a;
+      bv[c] = b;
 #pragma unroll
       for (int i = 0; i <= P; ++i) acc[c][i] += mcol[i] * b + kcol[i] * a + (i == k ? d : CT(0));
     }
     if (k == P) {
-      // cell ez = (rel - 1) / P + ezs complete: planes ez P + i, i < P, are final
+      // cell ez complete: planes ez P + i, i < P, are final
       const int ez = (rel - 1) / P + ezs;
       if (ez >= ez0) {
 #pragma unroll
@@ -286,34 +342,13 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
         }
       }
       // this vertex plane is also node 0 of the next cell
-      CT m0[P1], k0[P1];
-#pragma unroll
-      for (int i = 0; i <= P; ++i) {
-        m0[i] = half * MT(i, 0);
-        k0[i] = half * KT(i, 0);
-      }
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
-        const int col = tid + c * NT;
-        CT a = 0, b = 0;
-        if (col < NCOL) {
-          const int jj = col % J;
-          const int xl = (col / J) % BX;
-          const int yl = col / (J * BX);
-          a = sA[yl][xl][jj];
-          b = sB[yl][xl][jj];
-        }
         const CT carry = acc[c][P];
 #pragma unroll
-        for (int i = 0; i <= P; ++i) acc[c][i] = (i == 0 ? carry : CT(0)) + m0[i] * b + k0[i] * a;
+        for (int i = 0; i <= P; ++i)
+          acc[c][i] = (i == 0 ? carry : CT(0)) + half * (MT(i, 0) * bv[c] + KT(i, 0) * av[c]);
       }
-    }
-#pragma unroll
-    for (int t = 0; t < XPT; ++t) {
-#pragma unroll
-      for (int q = 0; q <= 2 * P; ++q) cur[t][q] = nxt[t][q];
-#pragma unroll
-      for (int q = 0; q < P; ++q) vcur[t][q] = vnxt[t][q];
     }
     buf ^= 1;
   }
@@ -323,10 +358,9 @@ namespace {
 
 template <typename T, int P, int J>
 fe_status launch_typed(const Mesh& m, KParams& prm, hipStream_t s) {
-  constexpr int NT = 512;
-  constexpr int BE = TileShape<P>::BE;
-  prm.tiles_x = (m.n + BE - 1) / BE;
-  prm.tiles_y = prm.tiles_x;
+  constexpr int NT = 256;
+  prm.tiles_x = (m.n + TileShape<P>::BEX - 1) / TileShape<P>::BEX;
+  prm.tiles_y = (m.n + TileShape<P>::BEY - 1) / TileShape<P>::BEY;
   prm.jchunks = (prm.nv + J - 1) / J;
   const long long base = (long long)prm.tiles_x * prm.tiles_y * prm.jchunks;
   // enough workgroups to fill 256 CUs several times; each z-segment re-walks one

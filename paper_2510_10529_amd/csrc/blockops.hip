@@ -287,6 +287,11 @@ __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
     y[i] = val;
 }
 
+__global__ void fill_f32_kernel(float* __restrict__ y, float val, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = val;
+}
+
 unsigned stream_grid(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192)); }
 
 }  // namespace
@@ -425,18 +430,32 @@ size_t project_work_bytes(int64_t N, int k, int nv) {
   return gram_work_bytes(N, k, nv) + (size_t)k * nv * sizeof(double) + 256;
 }
 
-fe_status project_out(const double* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s) {
+fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s) {
   if (k > 64 || nv > 64) return fail(FE_EINVAL, "projection: blocks wider than 64 columns are not supported");
-  if (f32) return fail(FE_EINVAL, "projection: FP32 blocks use the float projection");
   char* w = static_cast<char*>(work);
   double* G = reinterpret_cast<double*>(w);
   void* gw = w + (((size_t)k * nv * sizeof(double) + 255) / 256) * 256;
-  fe_status st = gram(Psi, k, X, nv, N, k, nv, false, G, gw, s);
+  fe_status st = gram(Psi, k, X, nv, N, k, nv, f32, G, gw, s);
   if (st != FE_OK) return st;
   const unsigned grid = (unsigned)((N + 63) / 64);
-  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, Psi, k, (long long)N, k, G, nv, -1.0, 1.0,
-                     static_cast<const double*>(X), static_cast<double*>(X), nv);
+  if (f32)
+    hipLaunchKernelGGL(rotate_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(Psi), k,
+                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const float*>(X), static_cast<float*>(X), nv);
+  else
+    hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(Psi), k,
+                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const double*>(X), static_cast<double*>(X), nv);
   INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(stream_grid(n)), dim3(256), 0, s, y, val, (long long)n);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  INVDFT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
   return FE_OK;
 }
 

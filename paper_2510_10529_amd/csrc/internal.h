@@ -98,7 +98,9 @@ fe_status fill(double* y, double val, int64_t n, hipStream_t s);
 
 // Projection X <- X - Psi (Psi^T X) (Psi: N x k, ld k; X: N x nv, ld nv). work: gram work + k*nv.
 size_t project_work_bytes(int64_t N, int k, int nv);
-fe_status project_out(const double* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work,
-                      hipStream_t s);
+// f32: Psi and X are float blocks (products accumulated in FP64).
+fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s);
+fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s);
+fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace invdft

@@ -23,15 +23,21 @@ int mr_state_active();
 int mr_state_invbeta();
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s);
 size_t mr_dots_work_bytes(int64_t nf, int k);
-fe_status mr_dots(const double* z, const double* y, const double* r1, int k, int64_t nf, double* d1, double* d2,
+template <typename T>
+fe_status mr_dots(const T* z, const T* y, const T* r1, int k, int64_t nf, double* d1, double* d2,
                   double* partial, hipStream_t s);
 fe_status mr_alfa(double* st, const double* d1, const double* d2, int k, bool first, hipStream_t s);
 fe_status mr_givens(double* st, const double* dot_r_z, int k, double tol, hipStream_t s);
-fe_status mr_resid_precond(double* y, double* r1, const double* r2, const double* st, const double* dinv, int k,
+template <typename T>
+fe_status mr_resid_precond(T* y, T* r1, const T* r2, const double* st, const double* dinv, int k,
                            int64_t nf, hipStream_t s);
-fe_status mr_update(const double* zold, double* w1, const double* w2, double* x, const double* st, int k, int64_t nf,
+template <typename T>
+fe_status mr_update(const T* zold, T* w1, const T* w2, T* x, const double* st, int k, int64_t nf,
                     hipStream_t s);
-fe_status k_precond(const double* x, const double* dinv, int k, int64_t nf, double* y, hipStream_t s);
+template <typename T>
+fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hipStream_t s);
+fe_status k_add_f32(const float* d, double* q, int64_t total, hipStream_t s);
+fe_status k_mask_cols(float* r, const double* rr, const double* bb, double tol, int k, int64_t nf, hipStream_t s);
 fe_status k_sub_from(const double* b, double* r, int64_t total, hipStream_t s);
 
 }  // namespace invdft

@@ -216,8 +216,9 @@ __global__ void mr_givens_kernel(double* __restrict__ st, const double* __restri
 }
 
 // d1 = z.y and d2 = z.r1 column-wise partials (two dots in one pass)
-__global__ __launch_bounds__(256) void mr_dots_kernel(const double* __restrict__ z, const double* __restrict__ y,
-                                                      const double* __restrict__ r1, int k, long long nf,
+template <typename T>
+__global__ __launch_bounds__(256) void mr_dots_kernel(const T* __restrict__ z, const T* __restrict__ y,
+                                                      const T* __restrict__ r1, int k, long long nf,
                                                       long long per, double* __restrict__ p1,
                                                       double* __restrict__ p2) {
   __shared__ double red1[256], red2[256];
@@ -228,9 +229,9 @@ __global__ __launch_bounds__(256) void mr_dots_kernel(const double* __restrict__
   double s1 = 0.0, s2 = 0.0;
   if (j < k)
     for (long long a = b0 + sub; a < b1; a += 4) {
-      const double zz = z[a * k + j];
-      s1 += zz * y[a * k + j];
-      s2 += zz * r1[a * k + j];
+      const double zz = (double)z[a * k + j];
+      s1 += zz * (double)y[a * k + j];
+      s2 += zz * (double)r1[a * k + j];
     }
   red1[threadIdx.x] = s1;
   red2[threadIdx.x] = s2;
@@ -242,32 +243,35 @@ __global__ __launch_bounds__(256) void mr_dots_kernel(const double* __restrict__
 }
 
 // rnew = y - c1 r1 - c2 r2 (stored over r1) ; u = rnew / D (stored over y)
-__global__ void mr_resid_precond_kernel(double* __restrict__ y, double* __restrict__ r1,
-                                        const double* __restrict__ r2, const double* __restrict__ st,
+template <typename T>
+__global__ void mr_resid_precond_kernel(T* __restrict__ y, T* __restrict__ r1,
+                                        const T* __restrict__ r2, const double* __restrict__ st,
                                         const double* __restrict__ dinv, int k, long long nf) {
   const long long total = nf * k;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(e % k);
     const long long a = e / k;
     if (!(st[S_ACTIVE * k + j] > 0.0)) continue;
-    const double rn = y[e] - st[S_C1 * k + j] * r1[e] - st[S_C2 * k + j] * r2[e];
-    r1[e] = rn;
-    y[e] = rn * dinv[a];
+    const double rn = (double)y[e] - st[S_C1 * k + j] * (double)r1[e] - st[S_C2 * k + j] * (double)r2[e];
+    r1[e] = (T)rn;
+    y[e] = (T)(rn * dinv[a]);
   }
 }
 
 // w_new = (z_old / beta_old - oldeps w1 - delta w2) / gamma ; x += phi w_new  (w_new stored over w1)
-__global__ void mr_update_kernel(const double* __restrict__ zold, double* __restrict__ w1,
-                                 const double* __restrict__ w2, double* __restrict__ x,
+template <typename T>
+__global__ void mr_update_kernel(const T* __restrict__ zold, T* __restrict__ w1,
+                                 const T* __restrict__ w2, T* __restrict__ x,
                                  const double* __restrict__ st, int k, long long nf) {
   const long long total = nf * k;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(e % k);
     const double ig = st[S_INVGAMMA * k + j];
     if (ig == 0.0) continue;  // frozen column (converged before this step)
-    const double wn = (zold[e] * st[S_INVBETA_OLD * k + j] - st[S_OLDEPS * k + j] * w1[e] - st[S_DELTA * k + j] * w2[e]) * ig;
-    w1[e] = wn;
-    x[e] += st[S_PHI * k + j] * wn;
+    const double wn = ((double)zold[e] * st[S_INVBETA_OLD * k + j] - st[S_OLDEPS * k + j] * (double)w1[e] -
+                       st[S_DELTA * k + j] * (double)w2[e]) * ig;
+    w1[e] = (T)wn;
+    x[e] = (T)((double)x[e] + st[S_PHI * k + j] * wn);
   }
 }
 
@@ -282,11 +286,28 @@ __global__ void dinv_kernel(const double* __restrict__ kd1, const double* __rest
 }
 
 // y = x / D row-wise (block)
-__global__ void precond_kernel(const double* __restrict__ x, const double* __restrict__ dinv, int k, long long nf,
-                               double* __restrict__ y) {
+template <typename T>
+__global__ void precond_kernel(const T* __restrict__ x, const double* __restrict__ dinv, int k, long long nf,
+                               T* __restrict__ y) {
   const long long total = nf * k;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
-    y[e] = x[e] * dinv[e / k];
+    y[e] = (T)((double)x[e] * dinv[e / k]);
+}
+
+// q += (double) d  (refinement update from the FP32 correction)
+__global__ void add_f32_kernel(const float* __restrict__ d, double* __restrict__ q, long long total) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
+    q[e] += (double)d[e];
+}
+
+// columns whose relative residual is at or below tol get a zero right-hand side (they stay frozen)
+__global__ void mask_cols_kernel(float* __restrict__ r, const double* __restrict__ rr, const double* __restrict__ bb,
+                                 double tol, int k, long long nf) {
+  const long long total = nf * k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % k);
+    if (rr[j] <= tol * tol * bb[j]) r[e] = 0.0f;
+  }
 }
 
 // r = b - r (in place): residual from r = A q
@@ -368,13 +389,14 @@ fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
   return FE_OK;
 }
 
-fe_status mr_dots(const double* z, const double* y, const double* r1, int k, int64_t nf, double* d1, double* d2,
+template <typename T>
+fe_status mr_dots(const T* z, const T* y, const T* r1, int k, int64_t nf, double* d1, double* d2,
                   double* partial, hipStream_t s) {
   const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 1023) / 1024, 1024));
   const long long per = (nf + nblk - 1) / nblk;
   double* p1 = partial;
   double* p2 = partial + (size_t)nblk * k;
-  hipLaunchKernelGGL(mr_dots_kernel, dim3(nblk), dim3(256), 0, s, z, y, r1, k, (long long)nf, per, p1, p2);
+  hipLaunchKernelGGL(mr_dots_kernel<T>, dim3(nblk), dim3(256), 0, s, z, y, r1, k, (long long)nf, per, p1, p2);
   INVDFT_HIP(hipGetLastError());
   return sum_columns(p1, nblk, k, d1, s) == FE_OK ? sum_columns(p2, nblk, k, d2, s) : FE_EDEVICE;
 }
@@ -396,26 +418,56 @@ fe_status mr_givens(double* st, const double* dot_r_z, int k, double tol, hipStr
   return FE_OK;
 }
 
-fe_status mr_resid_precond(double* y, double* r1, const double* r2, const double* st, const double* dinv, int k,
+template <typename T>
+fe_status mr_resid_precond(T* y, T* r1, const T* r2, const double* st, const double* dinv, int k,
                            int64_t nf, hipStream_t s) {
-  hipLaunchKernelGGL(mr_resid_precond_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, y, r1, r2, st, dinv, k,
+  hipLaunchKernelGGL(mr_resid_precond_kernel<T>, dim3(grid_for(nf * k)), dim3(256), 0, s, y, r1, r2, st, dinv, k,
                      (long long)nf);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
-fe_status mr_update(const double* zold, double* w1, const double* w2, double* x, const double* st, int k, int64_t nf,
+template <typename T>
+fe_status mr_update(const T* zold, T* w1, const T* w2, T* x, const double* st, int k, int64_t nf,
                     hipStream_t s) {
-  hipLaunchKernelGGL(mr_update_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, zold, w1, w2, x, st, k, (long long)nf);
+  hipLaunchKernelGGL(mr_update_kernel<T>, dim3(grid_for(nf * k)), dim3(256), 0, s, zold, w1, w2, x, st, k, (long long)nf);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
-fe_status k_precond(const double* x, const double* dinv, int k, int64_t nf, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(precond_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, x, dinv, k, (long long)nf, y);
+template <typename T>
+fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hipStream_t s) {
+  hipLaunchKernelGGL(precond_kernel<T>, dim3(grid_for(nf * k)), dim3(256), 0, s, x, dinv, k, (long long)nf, y);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
+
+fe_status k_add_f32(const float* d, double* q, int64_t total, hipStream_t s) {
+  hipLaunchKernelGGL(add_f32_kernel, dim3(grid_for(total)), dim3(256), 0, s, d, q, (long long)total);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status k_mask_cols(float* r, const double* rr, const double* bb, double tol, int k, int64_t nf, hipStream_t s) {
+  hipLaunchKernelGGL(mask_cols_kernel, dim3(grid_for(nf * k)), dim3(256), 0, s, r, rr, bb, tol, k, (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+template fe_status mr_dots<double>(const double*, const double*, const double*, int, int64_t, double*, double*,
+                                   double*, hipStream_t);
+template fe_status mr_dots<float>(const float*, const float*, const float*, int, int64_t, double*, double*, double*,
+                                  hipStream_t);
+template fe_status mr_resid_precond<double>(double*, double*, const double*, const double*, const double*, int,
+                                            int64_t, hipStream_t);
+template fe_status mr_resid_precond<float>(float*, float*, const float*, const double*, const double*, int, int64_t,
+                                           hipStream_t);
+template fe_status mr_update<double>(const double*, double*, const double*, double*, const double*, int, int64_t,
+                                     hipStream_t);
+template fe_status mr_update<float>(const float*, float*, const float*, float*, const double*, int, int64_t,
+                                    hipStream_t);
+template fe_status k_precond<double>(const double*, const double*, int, int64_t, double*, hipStream_t);
+template fe_status k_precond<float>(const float*, const double*, int, int64_t, float*, hipStream_t);
 
 fe_status k_sub_from(const double* b, double* r, int64_t total, hipStream_t s) {
   hipLaunchKernelGGL(sub_from_kernel, dim3(grid_for(total)), dim3(256), 0, s, b, r, (long long)total);

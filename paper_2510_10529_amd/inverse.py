@@ -1,0 +1,238 @@
+"""Inverse-DFT driver: the loss L(u) as a torch.autograd.Function whose backward
+is the adjoint solve, and an L-BFGS loop on the nodal XC potential u (Eq. 21).
+
+Forward (Sec. 3.2.2): v = v_fixed + u; Chebyshev-filtered subspace iteration to
+the residual tolerance; density, loss and adjoint right-hand side (Eqs. 1, 4, 7).
+Backward: optionally recompute the orbitals (from the warm-start block, so they
+need not be kept between forward and backward), solve the adjoint equations by
+batched projected MINRES (Eq. 20) and form g_b = sum_i psi_{b,i} q_{b,i} (Eq. 22).
+
+Every operation on device vectors is a call into libinvdft.so; torch supplies the
+buffers and the stream.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+from . import api
+
+
+@dataclass
+class SolverOptions:
+    degree: int = 40                 # Chebyshev filter degree
+    tol_eig: float = 1e-9            # max residual of the occupied Ritz pairs
+    tol_adj: float = 1e-10           # relative residual of every adjoint column
+    maxpass: int = 200
+    maxit_adj: int = 20000
+    filter_prec: str = "f64"         # "f64" | "f32"
+    adjoint_prec: str = "f64"        # "f64" | "f32" (FP32 MINRES + FP64 refinement)
+    switch_tol: float = 1e-4         # reduced-precision filter until the residual is below this
+    recompute: bool = False          # recompute orbitals in backward instead of keeping them
+    tau_bc: float = 0.0
+    adaptive: bool = False           # t_eig = e_L2^2 / c_eig, t_ad = e_L2^2 / c_ad (Table 1 defaults)
+    c_eig: float = 1e2
+    c_ad: float = 1e5
+
+
+@dataclass
+class Stats:
+    passes: list = field(default_factory=list)
+    adj_iters: list = field(default_factory=list)
+    t_forward: float = 0.0
+    t_adjoint: float = 0.0
+    n_forward: int = 0
+    n_backward: int = 0
+
+
+class InverseProblem:
+    """One inverse-DFT problem on one GPU: mesh, fixed potential, target density."""
+
+    def __init__(self, mesh: api.Mesh, v_fixed: torch.Tensor, rho_data: torch.Tensor, n_elec: int,
+                 X0: torch.Tensor, opts: SolverOptions | None = None):
+        self.mesh = mesh
+        self.v_fixed = v_fixed
+        self.rho_data = rho_data
+        self.nocc = n_elec // 2
+        self.occ = [2.0] * self.nocc
+        self.opts = opts or SolverOptions()
+        self.nv = X0.shape[1]
+        self.X = X0.clone()                    # FP64 warm-start block (Ritz vectors)
+        self.v = torch.empty_like(v_fixed)
+        self.eig = None
+        self.stats = Stats()
+        dev = X0.device
+        o = self.opts
+        self.work_eig = api._work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, self.nv, o.filter_prec), dev)
+        self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
+        self.work_lg = api._work(mesh.workspace_bytes(L.FE_OP_LOSS_GRAD, self.nocc), dev)
+        self.last_loss = None
+
+    # ------------------------------------------------------------------ pieces
+    def set_potential(self, u: torch.Tensor):
+        self.v.copy_(self.v_fixed)                  # device copy
+        api.axpby(1.0, u, 1.0, self.v)              # v = v_fixed + u
+
+    def tolerances(self):
+        o = self.opts
+        if o.adaptive and self.last_loss is not None:
+            e2 = self.last_loss
+            return max(min(o.tol_eig, e2 / o.c_eig), 1e-12), max(min(o.tol_adj, e2 / o.c_ad), 1e-13)
+        return o.tol_eig, o.tol_adj
+
+    def eigensolve(self, tol_eig):
+        o = self.opts
+        t0 = time.perf_counter()
+        r = api.ks_eigensolve(self.mesh, self.v, self.X, self.nocc, o.degree, tol_eig, o.maxpass,
+                              prec=o.filter_prec, switch_tol=o.switch_tol, work=self.work_eig)
+        torch.cuda.current_stream().synchronize()
+        self.stats.t_forward += time.perf_counter() - t0
+        self.stats.passes.append(r.passes)
+        self.stats.n_forward += 1
+        if r.status not in (L.FE_OK,):
+            raise L.FEError(r.status, "ks_eigensolve")
+        self.eig = r.eig
+        return r
+
+    def psi(self):
+        return self.X[:, :self.nocc].contiguous()
+
+    def loss_and_rhs(self, Psi):
+        rho, B, loss = api.loss_grad(self.mesh, Psi, self.occ, self.rho_data, work=self.work_lg)
+        self.last_loss = loss
+        return rho, B, loss
+
+    def gradient(self, Psi, B):
+        o = self.opts
+        _, tol_adj = self.tolerances()
+        t0 = time.perf_counter()
+        Q, ar = api.adjoint_solve(self.mesh, self.v, Psi, self.eig[:self.nocc], B, tol=tol_adj,
+                                  maxit=o.maxit_adj, prec=o.adjoint_prec, work=self.work_adj)
+        g = api.loss_grad(self.mesh, Psi, self.occ, self.rho_data, Q=Q, tau_bc=o.tau_bc, work=self.work_lg)
+        torch.cuda.current_stream().synchronize()
+        self.stats.t_adjoint += time.perf_counter() - t0
+        self.stats.adj_iters.append(max(ar.iters))
+        self.stats.n_backward += 1
+        if ar.status != L.FE_OK:
+            raise L.FEError(ar.status, "adjoint_solve")
+        return g
+
+    def evaluate(self, u: torch.Tensor, want_grad=True):
+        """L(u) and dL/du, without autograd."""
+        self.set_potential(u)
+        tol_eig, _ = self.tolerances()
+        self.eigensolve(tol_eig)
+        Psi = self.psi()
+        rho, B, loss = self.loss_and_rhs(Psi)
+        if not want_grad:
+            return loss, None
+        return loss, self.gradient(Psi, B)
+
+
+class InvDFTLoss(torch.autograd.Function):
+    """L(u) with the adjoint solve as its hand-written backward (Eqs. 7, 11, 20, 22)."""
+
+    @staticmethod
+    def forward(ctx, u, prob: InverseProblem):
+        prob.set_potential(u)
+        tol_eig, _ = prob.tolerances()
+        prob.eigensolve(tol_eig)
+        Psi = prob.psi()
+        rho, B, loss = prob.loss_and_rhs(Psi)
+        ctx.prob = prob
+        if prob.opts.recompute:
+            ctx.save_for_backward(u)               # orbitals are recomputed in backward
+        else:
+            ctx.save_for_backward(u, Psi, B)
+        return torch.tensor(loss, dtype=torch.float64, device=u.device)
+
+    @staticmethod
+    def backward(ctx, gL):
+        prob = ctx.prob
+        if prob.opts.recompute:
+            (u,) = ctx.saved_tensors
+            prob.set_potential(u)
+            tol_eig, _ = prob.tolerances()
+            prob.eigensolve(tol_eig)             # warm block is already converged: ~1 pass
+            Psi = prob.psi()
+            _, B, _ = prob.loss_and_rhs(Psi)
+        else:
+            u, Psi, B = ctx.saved_tensors
+        g = prob.gradient(Psi, B)
+        api.axpby(0.0, g, float(gL), g)            # g <- gL * g
+        return g, None
+
+
+def lbfgs(prob: InverseProblem, u0: torch.Tensor, maxiter: int = 30, history: int = 10,
+          callback=None, use_autograd: bool = True):
+    """L-BFGS (Nocedal 1980; Eq. 21) with Armijo backtracking, on device vectors.
+
+    The two-loop recursion and every vector update run through fe_dot / fe_axpby.
+    Returns (u, list of losses).
+    """
+    work = api._work(65536, u0.device)
+    u = u0.clone()
+
+    def fg(x):
+        if use_autograd:
+            xr = x.detach().clone().requires_grad_(True)
+            loss = InvDFTLoss.apply(xr, prob)
+            loss.backward()
+            return float(loss), xr.grad.detach()
+        return prob.evaluate(x)
+
+    f, g = fg(u)
+    S, Yh, RHO = [], [], []
+    losses = [f]
+    d = torch.empty_like(u)
+    u_new = torch.empty_like(u)
+    for it in range(maxiter):
+        # two-loop recursion: d = -H g
+        d.copy_(g)
+        alphas = []
+        for s, y, rho in zip(reversed(S), reversed(Yh), reversed(RHO)):
+            a = rho * api.dot(s, d, work)
+            api.axpby(-a, y, 1.0, d)
+            alphas.append(a)
+        if S:
+            gamma = api.dot(S[-1], Yh[-1], work) / api.dot(Yh[-1], Yh[-1], work)
+        else:
+            gamma = 1.0 / math.sqrt(max(api.dot(g, g, work), 1e-300))
+        api.axpby(0.0, d, gamma, d)
+        for (s, y, rho), a in zip(zip(S, Yh, RHO), reversed(alphas)):
+            b = rho * api.dot(y, d, work)
+            api.axpby(a - b, s, 1.0, d)
+        api.axpby(0.0, d, -1.0, d)
+        gd = api.dot(g, d, work)
+        if gd >= 0:                                 # not a descent direction: restart
+            S.clear(); Yh.clear(); RHO.clear()
+            d.copy_(g)
+            api.axpby(0.0, d, -1.0 / math.sqrt(max(api.dot(g, g, work), 1e-300)), d)
+            gd = api.dot(g, d, work)
+        step = 1.0
+        for _ in range(20):
+            u_new.copy_(u)
+            api.axpby(step, d, 1.0, u_new)
+            f_new, g_new = fg(u_new)
+            if f_new <= f + 1e-4 * step * gd:
+                break
+            step *= 0.5
+        s = u_new.clone()
+        api.axpby(-1.0, u, 1.0, s)
+        y = g_new.clone()
+        api.axpby(-1.0, g, 1.0, y)
+        sy = api.dot(s, y, work)
+        if sy > 1e-300:
+            S.append(s); Yh.append(y); RHO.append(1.0 / sy)
+            if len(S) > history:
+                S.pop(0); Yh.pop(0); RHO.pop(0)
+        u.copy_(u_new)
+        f, g = f_new, g_new
+        losses.append(f)
+        if callback:
+            callback(it, f, u)
+    return u, losses
