@@ -7,12 +7,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "internal.h"
 #include "krylov.h"
+#include "ref_tables.h"
 
 struct fe_mesh_s {
   invdft::Mesh m;
@@ -229,6 +231,8 @@ EigWork eig_layout(Bump& bp, const Mesh& m, int nv, int ld, fe_prec prec) {
 // Work blocks of one MINRES solve in storage type T (FP64 or FP32).
 struct MRWork {
   void *R1, *R2, *Z, *Y, *Wa, *Wb, *X;   // X: the solution of the inner solve (FP32 path only)
+  void* Qw;                              // compacted solution block
+  int* map;                              // column map of a compaction (device)
   double *dinv, *st, *d1, *d2, *bnorm, *dots, *pw;
   // FP32 refinement extras
   float* Psif;    // FP32 copy of Psi
@@ -245,6 +249,8 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
   w.Y = bp.take<char>(blk * es);
   w.Wa = bp.take<char>(blk * es);
   w.Wb = bp.take<char>(blk * es);
+  w.Qw = bp.take<char>(blk * es);
+  w.map = bp.take<int>(64);
   w.dinv = bp.take<double>(m.nf);
   w.st = bp.take<double>((size_t)mr_state_count() * k);
   w.d1 = bp.take<double>(k);
@@ -270,72 +276,116 @@ fe_status fill_t<float>(float* y, int64_t n, hipStream_t s) { return fill_f32(y,
 
 // MINRES (Paige and Saunders 1975) on P (H - eps_i) P q_i = b_i for all columns in lockstep,
 // preconditioner P D^{-1} P. Blocks of type T; every per-column scalar in FP64 on the device.
-// On return `iters` holds per-column iteration counts, `active` the still-unconverged flags.
+// Columns that have converged are dropped from every block (and from the operator apply)
+// once enough of them have: the solve's cost then follows the still-active columns.
+// On return `iters` holds per-column iteration counts, `active` the still-unconverged flags
+// (both in the original column order).
 template <typename T>
-fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double* eps_h, int k, const T* B, T* Q,
+fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double* eps_h, int k0, const T* B, T* Q,
                       double tol, int maxit, MRWork& w, std::vector<double>& iters, std::vector<double>& active,
                       hipStream_t s) {
   const int64_t nf = m.nf;
-  const size_t blk = (size_t)nf * k;
   const bool f32 = sizeof(T) == sizeof(float);
   const fe_prec prec = f32 ? FE_F32 : FE_F64;
+  const int SC = mr_state_count();
   fe_status st;
-  if ((st = fill_t<T>(Q, blk, s)) != FE_OK) return st;
-  if ((st = fill_t<T>(static_cast<T*>(w.Wa), blk, s)) != FE_OK) return st;
-  if ((st = fill_t<T>(static_cast<T*>(w.Wb), blk, s)) != FE_OK) return st;
-  if ((st = copy_bytes(B, w.R1, blk * sizeof(T), s)) != FE_OK) return st;
-  if ((st = copy_bytes(B, w.R2, blk * sizeof(T), s)) != FE_OK) return st;
-  // z = P D^{-1} b ; beta1 = sqrt(b.z)
-  if ((st = k_precond<T>(B, w.dinv, k, nf, static_cast<T*>(w.Z), s)) != FE_OK) return st;
-  if ((st = project_out(Psi, k, w.Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
-  if ((st = coldot(w.R1, w.Z, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
-  if ((st = mr_init(w.st, w.d1, k, s)) != FE_OK) return st;
+  int k = k0;
+  size_t blk = (size_t)nf * k;
   T *R1 = static_cast<T*>(w.R1), *R2 = static_cast<T*>(w.R2), *Z = static_cast<T*>(w.Z), *Y = static_cast<T*>(w.Y);
-  T *Wa = static_cast<T*>(w.Wa), *Wb = static_cast<T*>(w.Wb);
+  T *Wa = static_cast<T*>(w.Wa), *Wb = static_cast<T*>(w.Wb), *Qw = static_cast<T*>(w.Qw);
+  if ((st = fill_t<T>(Qw, blk, s)) != FE_OK) return st;
+  if ((st = fill_t<T>(Wa, blk, s)) != FE_OK) return st;
+  if ((st = fill_t<T>(Wb, blk, s)) != FE_OK) return st;
+  if ((st = copy_bytes(B, R1, blk * sizeof(T), s)) != FE_OK) return st;
+  if ((st = copy_bytes(B, R2, blk * sizeof(T), s)) != FE_OK) return st;
+  // z = P D^{-1} b ; beta1 = sqrt(b.z)
+  if ((st = k_precond<T>(B, w.dinv, k, nf, Z, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, k0, Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
+  if ((st = coldot(R1, Z, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = mr_init(w.st, w.d1, k, s)) != FE_OK) return st;
+  std::vector<int> orig(k0);
+  for (int j = 0; j < k0; ++j) orig[j] = j;
+  std::vector<double> eps(eps_h, eps_h + k0);
+  iters.assign(k0, 0.0);
+  active.assign(k0, 1.0);
+  std::vector<double> act(k0), sth((size_t)SC * k0), stn((size_t)SC * k0);
   ApplyArgs aa{};
   aa.v = v;
-  aa.nv = k;
-  aa.ld = k;
   aa.alpha = 1.0;
-  aa.colshift = eps_h;
-  active.assign(k, 1.0);
   const int check_every = 8;
+  // writes the compact solution columns back to Q and records per-column counters
+  auto flush = [&](bool all_cols) -> fe_status {
+    fe_status st2;
+    INVDFT_HIP(hipMemcpyAsync(w.map, orig.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
+    if ((st2 = k_scatter_cols<T>(Qw, k, Q, k0, w.map, nf, s)) != FE_OK) return st2;
+    INVDFT_HIP(hipMemcpyAsync(sth.data(), w.st, (size_t)SC * k * sizeof(double), hipMemcpyDeviceToHost, s));
+    INVDFT_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) {
+      iters[orig[j]] = sth[(size_t)mr_state_iters() * k + j];
+      active[orig[j]] = sth[(size_t)mr_state_active() * k + j];
+    }
+    (void)all_cols;
+    return FE_OK;
+  };
   for (int it = 1; it <= maxit; ++it) {
-    // y = P (H - eps) (z / beta)
+    aa.nv = k;
+    aa.ld = k;
+    aa.colshift = eps.data();
+    // y = (H - eps) (z / beta) ; y <- P y
     aa.X = Z;
     aa.Y = Y;
     aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
     if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
-    if ((st = project_out(Psi, k, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k0, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
     // alfa = v.(y - c1 r1)
     if ((st = mr_dots<T>(Z, Y, R1, k, nf, w.d1, w.d2, w.dots, s)) != FE_OK) return st;
     if ((st = mr_alfa(w.st, w.d1, w.d2, k, it == 1, s)) != FE_OK) return st;
     // r_new = y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; u <- P u
     if ((st = mr_resid_precond<T>(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
-    if ((st = project_out(Psi, k, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k0, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
     if ((st = coldot(R2, Y, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
     if ((st = mr_givens(w.st, w.d1, k, tol, s)) != FE_OK) return st;
-    if ((st = mr_update<T>(Z, Wb, Wa, Q, w.st, k, nf, s)) != FE_OK) return st;
+    if ((st = mr_update<T>(Z, Wb, Wa, Qw, w.st, k, nf, s)) != FE_OK) return st;
     std::swap(Wa, Wb);
-    std::swap(Z, Y);
+    std::swap(Z, Y);  // Y now holds the previous z: free until the next apply
     if (it % check_every == 0 || it == maxit) {
-      INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
+      INVDFT_HIP(hipMemcpyAsync(act.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
       INVDFT_HIP(hipStreamSynchronize(s));
-      bool done = true;
-      for (int j = 0; j < k; ++j)
-        if (active[j] > 0.0) done = false;
-      if (done) break;
+      int na = 0;
+      for (int j = 0; j < k; ++j) na += act[j] > 0.0 ? 1 : 0;
+      if (na == 0 || it == maxit) break;
+      if (na <= k - std::max(4, k / 4)) {
+        // drop the converged columns: write them out, then compact every block and the state
+        if ((st = flush(false)) != FE_OK) return st;
+        std::vector<int> keep;
+        for (int j = 0; j < k; ++j)
+          if (act[j] > 0.0) keep.push_back(j);
+        INVDFT_HIP(hipMemcpyAsync(w.map, keep.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
+        T** blocks[6] = {&R1, &R2, &Z, &Wa, &Wb, &Qw};
+        for (T** bptr : blocks) {
+          if ((st = k_select_cols<T>(*bptr, k, Y, na, w.map, nf, s)) != FE_OK) return st;
+          std::swap(*bptr, Y);
+        }
+        for (int q = 0; q < SC; ++q)
+          for (int j = 0; j < na; ++j) stn[(size_t)q * na + j] = sth[(size_t)q * k + keep[j]];
+        INVDFT_HIP(hipMemcpyAsync(w.st, stn.data(), (size_t)SC * na * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<int> orig2(na);
+        std::vector<double> eps2(na);
+        for (int j = 0; j < na; ++j) {
+          orig2[j] = orig[keep[j]];
+          eps2[j] = eps[keep[j]];
+        }
+        orig.swap(orig2);
+        eps.swap(eps2);
+        k = na;
+        INVDFT_HIP(hipStreamSynchronize(s));  // host vectors above are sources of async copies
+      }
     }
   }
-  if ((st = project_out(Psi, k, Q, k, nf, f32, w.pw, s)) != FE_OK) return st;
-  iters.resize(k);
-  INVDFT_HIP(hipMemcpyAsync(iters.data(), w.st + (size_t)mr_state_iters() * k, k * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-  INVDFT_HIP(hipMemcpyAsync(active.data(), w.st + (size_t)mr_state_active() * k, k * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-  INVDFT_HIP(hipStreamSynchronize(s));
+  if ((st = flush(true)) != FE_OK) return st;
+  if ((st = project_out(Psi, k0, Q, k0, nf, f32, w.pw, s)) != FE_OK) return st;
   return FE_OK;
 }
 
@@ -405,6 +455,32 @@ fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
       for (int k = 0; k < P1; ++k)
         B[i * P1 + k] = 0.25 * (A[i * P1 + k] + A[k * P1 + i] + A[(p - i) * P1 + (p - k)] + A[(p - k) * P1 + (p - i)]);
     std::memcpy(A, B, sizeof(double) * P1 * P1);
+  }
+  // the kernels use compile-time unit-cell tables: check them against these run-time ones
+  {
+    double maxdiff = 0.0, scale = 0.0;
+    auto cmp = [&](const auto& tab) {
+      for (int i = 0; i < P1; ++i)
+        for (int k = 0; k < P1; ++k) {
+          maxdiff = std::max(maxdiff, std::fabs(tab.mt[i][k] - m.mt[i * P1 + k]));
+          maxdiff = std::max(maxdiff, std::fabs(tab.kt[i][k] - m.kt[i * P1 + k] * m.h * m.h));
+          scale = std::max(scale, std::fabs(tab.kt[i][k]));
+        }
+    };
+    switch (p) {
+      case 1: cmp(ref::Table<1>::value); break;
+      case 2: cmp(ref::Table<2>::value); break;
+      case 3: cmp(ref::Table<3>::value); break;
+      case 4: cmp(ref::Table<4>::value); break;
+      case 5: cmp(ref::Table<5>::value); break;
+      case 6: cmp(ref::Table<6>::value); break;
+      case 7: cmp(ref::Table<7>::value); break;
+      case 8: cmp(ref::Table<8>::value); break;
+    }
+    if (!(maxdiff <= 1e-13 * scale)) {
+      delete h;
+      return fail(FE_EDEVICE, "fe_mesh_create: compile-time element tables disagree with run-time ones");
+    }
   }
   m.x1.resize(n1);
   m.w1.resize(n1);
@@ -693,7 +769,8 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
   } else {
     // FP32 MINRES inner solves with FP64 iterative refinement: q += d, (H - eps) d = r in FP32,
     // r = b - (H - eps) q in FP64, until every column reaches tol.
-    const double tol_inner = std::max(tol, 1e-4);
+    double tol_inner = std::max(tol, 1e-4);
+    if (const char* e = std::getenv("INVDFT_INNER_TOL")) tol_inner = std::max(tol, std::atof(e));  // experiments
     if ((st = cast_block_to_f32(Psi, w.Psif, blk, s)) != FE_OK) return st;
     if ((st = fill(Q, 0.0, blk, s)) != FE_OK) return st;
     if ((st = copy_bytes(B, w.R64, blk * sizeof(double), s)) != FE_OK) return st;

@@ -31,6 +31,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "ref_tables.h"
 
 namespace invdft {
 
@@ -44,8 +45,8 @@ struct KParams {
   int zseg, tiles_x, tiles_y, jchunks, zsegs;
   int has_colshift;
   double alpha, beta, cshift;
-  double mt[kMaxP1 * kMaxP1];
-  double kt[kMaxP1 * kMaxP1];
+  double kscale;  // 1/(2 h^2): the kinetic accumulators hold 2 h^2 K~/2 X
+  double dscale;  // 2 h^2: the diagonal term is stored in the same units
   double colshift[kMaxShiftCols];
 };
 
@@ -58,26 +59,53 @@ struct KParams {
 #ifndef KS_APPLY_BEY5
 #define KS_APPLY_BEY5 1
 #endif
-template <int P>
+#ifndef KS_APPLY_FP64_M_SCALAR
+#define KS_APPLY_FP64_M_SCALAR 1
+#endif
+template <int P, typename T>
 struct TileShape {
   static constexpr int BEX = (P == 1) ? 4 : (P == 2) ? 4 : (P <= 5) ? 2 : 1;
-  static constexpr int BEY = (P == 1) ? 4 : (P == 2) ? 2 : (P <= 4) ? 2 : (P == 5) ? KS_APPLY_BEY5 : 1;
+  // at P = 5 the FP64 kernel is fastest with 2 x 2 cells, the FP32 one with 2 x 1
+  static constexpr int BEY = (P == 1) ? 4 : (P == 2) ? 2 : (P <= 4) ? 2 : (P == 5) ? (sizeof(T) == 8 ? 2 : KS_APPLY_BEY5) : 1;
 };
 
-// The scaled 1-D element matrices are symmetric and centrosymmetric
-// (A[i][k] = A[k][i] = A[P-i][P-k]: GLL nodes and weights are symmetric about
-// the cell centre). Indexing every entry through one canonical representative
-// lets the compiler keep only the distinct values (12 of 36 at P = 5) in scalar
-// registers; the host stores the average of the four copies there.
-__host__ __device__ constexpr int canon_index(int i, int k, int P) {
-  int a = i < k ? i : k, b = i < k ? k : i;
-  const int a2 = P - b, b2 = P - a;
-  if (a2 < a || (a2 == a && b2 < b)) {
-    a = a2;
-    b = b2;
+// Distinct entries of a symmetric, centrosymmetric (P+1)x(P+1) matrix: slot of (i, k).
+template <int P>
+struct Canon {
+  static constexpr int rep(int i, int k) {
+    int a = i < k ? i : k, b = i < k ? k : i;
+    const int a2 = P - b, b2 = P - a;
+    if (a2 < a || (a2 == a && b2 < b)) {
+      a = a2;
+      b = b2;
+    }
+    return a * (P + 1) + b;
   }
-  return a * (P + 1) + b;
-}
+  struct Map {
+    int slot[P + 1][P + 1];
+    int rep_of[(P + 1) * (P + 1)];
+    int count;
+  };
+  static constexpr Map make() {
+    Map m{};
+    int seen[(P + 1) * (P + 1)] = {};
+    for (int q = 0; q < (P + 1) * (P + 1); ++q) seen[q] = -1;
+    m.count = 0;
+    for (int i = 0; i <= P; ++i)
+      for (int k = 0; k <= P; ++k) {
+        const int r = rep(i, k);
+        if (seen[r] < 0) {
+          seen[r] = m.count;
+          m.rep_of[m.count] = r;
+          ++m.count;
+        }
+        m.slot[i][k] = seen[r];
+      }
+    return m;
+  }
+  static constexpr Map map = make();
+  static constexpr int N = map.count;
+};
 
 // Logical block order: column chunk fastest, then tile x, tile y, z-segment.
 // The hardware deals consecutive block ids round-robin to the 8 XCDs; this
@@ -89,11 +117,39 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
+// acc[c][i] += m~(i, k) b_c + k~ref(i, k) a_c (+ d_c for i = k), for the block-uniform
+// plane index k, unrolled per value of k so that every coefficient is a compile-time
+// constant of the unit-cell tables.
+template <typename CT, int P, int CPT, int NU, int K>
+__device__ __forceinline__ void z_acc_k(const CT (&cM)[NU], const CT (&cK)[NU], CT (&acc)[CPT][P + 1],
+                                        const CT (&av)[CPT], const CT (&bv)[CPT], const CT (&dv)[CPT]) {
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+      acc[c][i] = fma(cM[Canon<P>::map.slot[i][K]], bv[c], acc[c][i]);
+      acc[c][i] = fma(cK[Canon<P>::map.slot[i][K]], av[c], acc[c][i]);
+    }
+    acc[c][K] += dv[c];
+  }
+}
+
+template <typename CT, int P, int CPT, int NU, int K = 0>
+__device__ __forceinline__ void z_accumulate(int k, const CT (&cM)[NU], const CT (&cK)[NU], CT (&acc)[CPT][P + 1],
+                                             const CT (&av)[CPT], const CT (&bv)[CPT], const CT (&dv)[CPT]) {
+  if constexpr (K <= P) {
+    if (k == K)
+      z_acc_k<CT, P, CPT, NU, K>(cM, cK, acc, av, bv, dv);
+    else
+      z_accumulate<CT, P, CPT, NU, K + 1>(k, cM, cK, acc, av, bv, dv);
+  }
+}
+
 template <typename T, int P, int J, int NT>
 __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const KParams prm) {
   using CT = T;  // compute type = storage type (FP64 or FP32)
   constexpr int P1 = P + 1;
-  constexpr int BEX = TileShape<P>::BEX, BEY = TileShape<P>::BEY;
+  constexpr int BEX = TileShape<P, T>::BEX, BEY = TileShape<P, T>::BEY;
   constexpr int BX = BEX * P, BY = BEY * P;  // owned nodes per tile edge
   constexpr int NYI = (BEY + 1) * P + 1;     // input rows (owned + halo)
   constexpr int NXN = (BEX + 1) * P + 1;     // input nodes per row (owned + halo)
@@ -143,49 +199,91 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
   auto node_index = [&](int gx, int gy, int gz) -> long long {
     return (long long)(gx - 1) + (long long)n1 * ((long long)(gy - 1) + (long long)n1 * (gz - 1));
   };
-  auto MT = [&](int i, int k) { return (CT)prm.mt[canon_index(i, k, P)]; };
-  auto KT = [&](int i, int k) { return (CT)prm.kt[canon_index(i, k, P)]; };
+  // Coefficients. FP32: compile-time literals. FP64 (no 64-bit literal operands): the
+  // distinct entries are read once from an LDS table into registers, so the loop does
+  // not hold 2 x NU doubles in scalar registers.
+  constexpr int NU = Canon<P>::N;
+  __shared__ double sTab[2][NU];
+  if constexpr (sizeof(CT) == sizeof(double)) {
+    for (int q = tid; q < 2 * NU; q += NT) {
+      const int r = Canon<P>::map.rep_of[q % NU];
+      sTab[q / NU][q % NU] = (q < NU) ? ref::Table<P>::value.mt[r / (P + 1)][r % (P + 1)]
+                                      : ref::Table<P>::value.kt[r / (P + 1)][r % (P + 1)];
+    }
+    __syncthreads();
+  }
+  CT cM[NU], cK[NU];
+#pragma unroll
+  for (int q = 0; q < NU; ++q) {
+    if constexpr (sizeof(CT) == sizeof(double)) {
+      // split: mass entries stay scalar (uniform), stiffness entries in vector registers
+      const int r = Canon<P>::map.rep_of[q];
+      cM[q] = KS_APPLY_FP64_M_SCALAR ? (CT)ref::Table<P>::value.mt[r / (P + 1)][r % (P + 1)] : sTab[0][q];
+      cK[q] = sTab[1][q];
+    } else {
+      const int r = Canon<P>::map.rep_of[q];
+      cM[q] = (CT)ref::Table<P>::value.mt[r / (P + 1)][r % (P + 1)];
+      cK[q] = (CT)ref::Table<P>::value.kt[r / (P + 1)][r % (P + 1)];
+    }
+  }
+  auto MT = [&](int i, int k) { return cM[Canon<P>::map.slot[i][k]]; };
+  auto KT = [&](int i, int k) { return cK[Canon<P>::map.slot[i][k]]; };
 
-  // ---- plane loader: non-redundant 16-byte chunks into registers (prefetch), then LDS
+  // ---- plane loader: non-redundant 16-byte chunks into registers (prefetch), then LDS.
+  // The (x, y, column) part of every chunk's address is the same on all planes.
   T16 pre[LPT];
   double vpre[VPT];
+  long long coff[LPT];   // element offset of the chunk in plane gz = 1, or -1 when outside
+  int cfull[LPT];        // 1: whole chunk in range and 16-byte aligned
+  long long voff[VPT];
+  const long long plane_stride = (long long)n1 * n1;
+#pragma unroll
+  for (int t = 0; t < LPT; ++t) {
+    const int c = tid + t * NT;
+    coff[t] = -1;
+    cfull[t] = 0;
+    if (c < NCHUNK) {
+      const int part = c % CPN;
+      const int r = c / CPN;
+      const int gx = ex0 * P - P + r % NXN, gy = ey0 * P - P + r / NXN;
+      const int jb = j0 + part * EPC;
+      if (node_ok(gx) && node_ok(gy) && jb < nv) {
+        coff[t] = node_index(gx, gy, 1) * ld + jb;
+        cfull[t] = (vec_ok && jb + EPC <= nv) ? 1 : 0;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < VPT; ++t) {
+    const int o = tid + t * NT;
+    voff[t] = -1;
+    if (o < NVO) {
+      const int gx = ex0 * P + o % BX, gy = ey0 * P + o / BX;
+      if (node_ok(gx) && node_ok(gy)) voff[t] = node_index(gx, gy, 1);
+    }
+  }
   auto load_plane = [&](int gz) {
     const bool zok = node_ok(gz);
+    const long long zo = (long long)(gz - 1) * plane_stride;
 #pragma unroll
     for (int t = 0; t < LPT; ++t) {
-      const int c = tid + t * NT;
       T16 val;
 #pragma unroll
       for (int e = 0; e < EPC; ++e) val[e] = T(0);
-      if (c < NCHUNK && zok) {
-        const int part = c % CPN;
-        const int r = c / CPN;
-        const int xn = r % NXN;
-        const int yl = r / NXN;
-        const int gx = ex0 * P - P + xn, gy = ey0 * P - P + yl;
-        const int jb = j0 + part * EPC;
-        if (node_ok(gx) && node_ok(gy) && jb < nv) {
-          const T* src = X + node_index(gx, gy, gz) * ld + jb;
-          if (vec_ok && jb + EPC <= nv) {
-            val = *reinterpret_cast<const T16*>(src);
-          } else {
+      if (zok && coff[t] >= 0) {
+        const T* src = X + coff[t] + zo * ld;
+        if (cfull[t]) {
+          val = *reinterpret_cast<const T16*>(src);
+        } else {
+          const int jb = (int)((coff[t]) % ld);
 #pragma unroll
-            for (int e = 0; e < EPC; ++e) val[e] = (jb + e < nv) ? src[e] : T(0);
-          }
+          for (int e = 0; e < EPC; ++e) val[e] = (jb + e < nv) ? src[e] : T(0);
         }
       }
       pre[t] = val;
     }
 #pragma unroll
-    for (int t = 0; t < VPT; ++t) {
-      const int o = tid + t * NT;
-      double vv = 0.0;
-      if (o < NVO && zok) {
-        const int gx = ex0 * P + o % BX, gy = ey0 * P + o / BX;
-        if (node_ok(gx) && node_ok(gy)) vv = prm.v[node_index(gx, gy, gz)];
-      }
-      vpre[t] = vv;
-    }
+    for (int t = 0; t < VPT; ++t) vpre[t] = (zok && voff[t] >= 0) ? prm.v[voff[t] + zo] : 0.0;
   };
   auto store_plane = [&]() {
 #pragma unroll
@@ -216,7 +314,6 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
   store_plane();
   __syncthreads();
   int buf = 0;
-  const CT half = CT(0.5);
 #pragma unroll 1
   for (int gz = gz0; gz <= gz1; ++gz) {
     if (gz < gz1) load_plane(gz + 1);  // prefetch: in flight during this plane's passes
@@ -231,20 +328,18 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
       for (int k = 0; k <= 2 * P; ++k) in[k] = sIn[yl][exl * P + k][jj];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        CT u1 = 0, u2 = 0;
+        CT u1 = MT(i, 0) * in[P], u2 = KT(i, 0) * in[P];
 #pragma unroll
-        for (int k = 0; k <= P; ++k) {
-          u1 += MT(i, k) * in[P + k];
-          u2 += KT(i, k) * in[P + k];
+        for (int k = 1; k <= P; ++k) {
+          u1 = fma(MT(i, k), in[P + k], u1);
+          u2 = fma(KT(i, k), in[P + k], u2);
         }
         if (i == 0) {  // shared vertex: the left cell's row P as well
 #pragma unroll
-          for (int k = 0; k < P; ++k) {
-            u1 += MT(P, k) * in[k];
-            u2 += KT(P, k) * in[k];
+          for (int k = 0; k <= P; ++k) {
+            u1 = fma(MT(P, k), in[k], u1);
+            u2 = fma(KT(P, k), in[k], u2);
           }
-          u1 += MT(P, P) * in[P];
-          u2 += KT(P, P) * in[P];
         }
         sU1[yl][exl * P + i][jj] = u1;
         sU2[yl][exl * P + i][jj] = u2;
@@ -254,7 +349,7 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
         const double sh = prm.cshift + ((prm.has_colshift && j < nv) ? prm.colshift[j] : 0.0);
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          sD[buf][yl - P][exl * P + i][jj] = (CT)((sV[yl - P][exl * P + i] - sh) * (double)in[P + i]);
+          sD[buf][yl - P][exl * P + i][jj] = (CT)(prm.dscale * (sV[yl - P][exl * P + i] - sh) * (double)in[P + i]);
       }
     }
     __syncthreads();
@@ -272,17 +367,20 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        CT A = 0, B = 0;
+        CT A = MT(i, 0) * a1[P], B = MT(i, 0) * a2[P];
+        B = fma(KT(i, 0), a1[P], B);
 #pragma unroll
-        for (int k = 0; k <= P; ++k) {
-          A += MT(i, k) * a1[P + k];
-          B += MT(i, k) * a2[P + k] + KT(i, k) * a1[P + k];
+        for (int k = 1; k <= P; ++k) {
+          A = fma(MT(i, k), a1[P + k], A);
+          B = fma(MT(i, k), a2[P + k], B);
+          B = fma(KT(i, k), a1[P + k], B);
         }
         if (i == 0) {
 #pragma unroll
           for (int k = 0; k <= P; ++k) {
-            A += MT(P, k) * a1[k];
-            B += MT(P, k) * a2[k] + KT(P, k) * a1[k];
+            A = fma(MT(P, k), a1[k], A);
+            B = fma(MT(P, k), a2[k], B);
+            B = fma(KT(P, k), a1[k], B);
           }
         }
         sA[eyl * P + i][xl][jj] = A;
@@ -292,30 +390,25 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
     // the raw plane and potential were last read by this plane's x-pass (before the barrier above)
     if (gz < gz1) store_plane();
     __syncthreads();
-    // ---- z-step: plane gz is node k of the current cell (k = 0 only for the first plane)
+    // ---- z-step: plane gz is node k of the current cell (k = 0 only for the first plane).
+    // The accumulators hold 2 h^2 times the output (unit-cell tables; kscale on output);
+    // k is block-uniform, so the dispatch on it is a scalar branch.
     const int rel = gz - gz0;
     const int k = (rel == 0) ? 0 : ((rel - 1) % P) + 1;
-    CT mcol[P1], kcol[P1];
-#pragma unroll
-    for (int i = 0; i <= P; ++i) {
-      mcol[i] = half * (CT)prm.mt[canon_index(i, k, P)];
-      kcol[i] = half * (CT)prm.kt[canon_index(i, k, P)];
-    }
-    CT av[CPT], bv[CPT];
+    CT av[CPT], bv[CPT], dv[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int col = tid + c * NT;
-      av[c] = bv[c] = 0;
+      av[c] = bv[c] = dv[c] = 0;
       if (col >= NCOL) continue;
       const int jj = col % J;
       const int xl = (col / J) % BX;
       const int yl = col / (J * BX);
-      const CT a = sA[yl][xl][jj], b = sB[yl][xl][jj], d = sD[buf][yl][xl][jj];
-      av[c] = a;
-      bv[c] = b;
-#pragma unroll
-      for (int i = 0; i <= P; ++i) acc[c][i] += mcol[i] * b + kcol[i] * a + (i == k ? d : CT(0));
+      av[c] = sA[yl][xl][jj];
+      bv[c] = sB[yl][xl][jj];
+      dv[c] = sD[buf][yl][xl][jj];
     }
+    z_accumulate<CT, P, CPT, NU>(k, cM, cK, acc, av, bv, dv);
     if (k == P) {
       // cell ez complete: planes ez P + i, i < P, are final
       const int ez = (rel - 1) / P + ezs;
@@ -329,7 +422,7 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
           const int yl = col / (J * BX);
           const int gx = ex0 * P + xl, gy = ey0 * P + yl, j = j0 + jj;
           if (!node_ok(gx) || !node_ok(gy) || j >= nv) continue;
-          const CT scale = (CT)prm.alpha * (prm.colscale ? (CT)prm.colscale[j] : CT(1));
+          const CT scale = (CT)(prm.kscale * prm.alpha) * (prm.colscale ? (CT)prm.colscale[j] : CT(1));
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             const int gzo = ez * P + i;
@@ -347,7 +440,7 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
         const CT carry = acc[c][P];
 #pragma unroll
         for (int i = 0; i <= P; ++i)
-          acc[c][i] = (i == 0 ? carry : CT(0)) + half * (MT(i, 0) * bv[c] + KT(i, 0) * av[c]);
+          acc[c][i] = fma(KT(i, 0), av[c], fma(MT(i, 0), bv[c], i == 0 ? carry : CT(0)));
       }
     }
     buf ^= 1;
@@ -359,8 +452,8 @@ namespace {
 template <typename T, int P, int J>
 fe_status launch_typed(const Mesh& m, KParams& prm, hipStream_t s) {
   constexpr int NT = 256;
-  prm.tiles_x = (m.n + TileShape<P>::BEX - 1) / TileShape<P>::BEX;
-  prm.tiles_y = (m.n + TileShape<P>::BEY - 1) / TileShape<P>::BEY;
+  prm.tiles_x = (m.n + TileShape<P, T>::BEX - 1) / TileShape<P, T>::BEX;
+  prm.tiles_y = (m.n + TileShape<P, T>::BEY - 1) / TileShape<P, T>::BEY;
   prm.jchunks = (prm.nv + J - 1) / J;
   const long long base = (long long)prm.tiles_x * prm.tiles_y * prm.jchunks;
   // enough workgroups to fill 256 CUs several times; each z-segment re-walks one
@@ -410,8 +503,8 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
   prm.alpha = a.alpha;
   prm.beta = a.beta;
   prm.cshift = a.cshift;
-  std::memcpy(prm.mt, m.mt, sizeof(prm.mt));
-  std::memcpy(prm.kt, m.kt, sizeof(prm.kt));
+  prm.kscale = 0.5 / (m.h * m.h);
+  prm.dscale = 2.0 * m.h * m.h;
   if (a.colshift) {
     if (a.nv > kMaxShiftCols) return fail(FE_EINVAL, "ks_apply: per-column shifts limited to 256 columns");
     prm.has_colshift = 1;

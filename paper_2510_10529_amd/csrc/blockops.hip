@@ -109,18 +109,27 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(const T* __r
   }
 }
 
-// out[i][j] = sum over blocks (fixed order) of the partial tiles.
-__global__ void gram_reduce_kernel(const double* __restrict__ partial, int nblk, int ntiles, int nx, int ny,
-                                   double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// out[i][j] = sum over blocks of the partial tiles: one wavefront per entry, each lane sums
+// a fixed strided subset, then a fixed-order butterfly across the lanes (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ partial, int nblk, int ntiles,
+                                                          int nx, int ny, double* __restrict__ out) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (e >= nx * ny) return;
   const int i = e / ny, j = e % ny;
   const int tiles_j = (ny + kGramTile - 1) / kGramTile;
   const int tile = (i / kGramTile) * tiles_j + (j / kGramTile);
   const int off = (i % kGramTile) * kGramTile + (j % kGramTile);
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((long long)b * ntiles + tile) * kGramTile * kGramTile + off];
-  out[e] = s;
+  for (int b = lane; b < nblk; b += 64) s += partial[((long long)b * ntiles + tile) * kGramTile * kGramTile + off];
+  s = wave_sum(s);
+  if (lane == 0) out[e] = s;
 }
 
 int gram_blocks(long long N) {
@@ -223,12 +232,15 @@ __global__ __launch_bounds__(256) void resid_partial_kernel(const double* __rest
   }
 }
 
-__global__ void sum_partials_kernel(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial, int nblk, int nv,
+                                                           double* __restrict__ out) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= nv) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nv + j];
-  out[j] = s;
+  for (int b = lane; b < nblk; b += 64) s += partial[(long long)b * nv + j];
+  s = wave_sum(s);
+  if (lane == 0) out[j] = s;
 }
 
 __global__ void dot1_partial_kernel(const double* __restrict__ x, const double* __restrict__ y, long long n,
@@ -317,7 +329,7 @@ fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx
     hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(kGramThreads), 0, s, static_cast<const double*>(X),
                        ldx, static_cast<const double*>(Y), ldy, (long long)N, nx, ny, rpb, sym, partial);
   INVDFT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 255) / 256), dim3(256), 0, s, partial, nblk,
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 3) / 4), dim3(256), 0, s, partial, nblk,
                      tiles_i * tiles_j, nx, ny, out);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
@@ -349,7 +361,7 @@ fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f
     hipLaunchKernelGGL(coldot_partial_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(X),
                        static_cast<const double*>(Y), ld, (long long)N, nv, rpb, partial);
   INVDFT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, out);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -362,13 +374,13 @@ fe_status colresid(const double* HX, const double* X, const double* lam, int ld,
   hipLaunchKernelGGL(resid_partial_kernel, dim3(nblk, (nv + 63) / 64), dim3(256), 0, s, HX, X, lam, ld, (long long)N,
                      nv, rpb, partial);
   INVDFT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, out);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
 fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 255) / 256), dim3(256), 0, s, partial, nblk, nv, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, out);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

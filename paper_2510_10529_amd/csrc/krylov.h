@@ -37,6 +37,10 @@ fe_status mr_update(const T* zold, T* w1, const T* w2, T* x, const double* st, i
 template <typename T>
 fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hipStream_t s);
 fe_status k_add_f32(const float* d, double* q, int64_t total, hipStream_t s);
+template <typename T>
+fe_status k_select_cols(const T* src, int ko, T* dst, int kn, const int* map, int64_t nf, hipStream_t s);
+template <typename T>
+fe_status k_scatter_cols(const T* src, int kc, T* dst, int kf, const int* map, int64_t nf, hipStream_t s);
 fe_status k_mask_cols(float* r, const double* rr, const double* bb, double tol, int k, int64_t nf, hipStream_t s);
 fe_status k_sub_from(const double* b, double* r, int64_t total, hipStream_t s);
 

@@ -294,6 +294,28 @@ __global__ void precond_kernel(const T* __restrict__ x, const double* __restrict
     y[e] = (T)((double)x[e] * dinv[e / k]);
 }
 
+// dst[a, jn] = src[a, map[jn]] (dst has kn columns, src ko)
+template <typename T>
+__global__ void select_cols_kernel(const T* __restrict__ src, int ko, T* __restrict__ dst, int kn,
+                                   const int* __restrict__ map, long long nf) {
+  const long long total = nf * kn;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long a = e / kn;
+    dst[e] = src[a * ko + map[e % kn]];
+  }
+}
+
+// dst[a, map[jc]] = src[a, jc]  (scatter kc compact columns into a kf-wide block)
+template <typename T>
+__global__ void scatter_cols_kernel(const T* __restrict__ src, int kc, T* __restrict__ dst, int kf,
+                                    const int* __restrict__ map, long long nf) {
+  const long long total = nf * kc;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long a = e / kc;
+    dst[a * kf + map[e % kc]] = src[e];
+  }
+}
+
 // q += (double) d  (refinement update from the FP32 correction)
 __global__ void add_f32_kernel(const float* __restrict__ d, double* __restrict__ q, long long total) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
@@ -441,6 +463,27 @@ fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hip
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
+
+template <typename T>
+fe_status k_select_cols(const T* src, int ko, T* dst, int kn, const int* map, int64_t nf, hipStream_t s) {
+  hipLaunchKernelGGL(select_cols_kernel<T>, dim3(grid_for(nf * kn)), dim3(256), 0, s, src, ko, dst, kn, map,
+                     (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T>
+fe_status k_scatter_cols(const T* src, int kc, T* dst, int kf, const int* map, int64_t nf, hipStream_t s) {
+  hipLaunchKernelGGL(scatter_cols_kernel<T>, dim3(grid_for(nf * kc)), dim3(256), 0, s, src, kc, dst, kf, map,
+                     (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+template fe_status k_select_cols<double>(const double*, int, double*, int, const int*, int64_t, hipStream_t);
+template fe_status k_select_cols<float>(const float*, int, float*, int, const int*, int64_t, hipStream_t);
+template fe_status k_scatter_cols<double>(const double*, int, double*, int, const int*, int64_t, hipStream_t);
+template fe_status k_scatter_cols<float>(const float*, int, float*, int, const int*, int64_t, hipStream_t);
 
 fe_status k_add_f32(const float* d, double* q, int64_t total, hipStream_t s) {
   hipLaunchKernelGGL(add_f32_kernel, dim3(grid_for(total)), dim3(256), 0, s, d, q, (long long)total);
