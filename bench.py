@@ -122,6 +122,14 @@ def main():
     log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}")
     if args.apply_only:
         out = {}
+        # a plain streaming kernel of known size, for scaling the HBM byte counters:
+        # fe_axpby over 2^27 doubles reads 2 GiB and writes 1 GiB
+        xa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        ya = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            api.axpby(1.0, xa, 1.0, ya)
+        torch.cuda.synchronize()
+        del xa, ya
         for prec, cols in (("f64", nocc), ("f32", nv)):
             ms, b = apply_timing(api, mesh, v_fixed, cols, prec, reps=args.reps)
             out[f"ks_apply_{prec}"] = {"columns": cols, "ms": ms, "algorithmic_bytes": b,

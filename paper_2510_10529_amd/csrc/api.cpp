@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "krylov.h"
+#include "minres_fused.h"
 #include "ref_tables.h"
 
 struct fe_mesh_s {
@@ -233,6 +234,7 @@ struct MRWork {
   void *R1, *R2, *Z, *Y, *Wa, *Wb, *X;   // X: the solution of the inner solve (FP32 path only)
   void* Qw;                              // compacted solution block
   int* map;                              // column map of a compaction (device)
+  void* fused;                           // partial sums of the fused passes
   double *dinv, *st, *d1, *d2, *bnorm, *dots, *pw;
   // FP32 refinement extras
   float* Psif;    // FP32 copy of Psi
@@ -251,6 +253,7 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
   w.Wb = bp.take<char>(blk * es);
   w.Qw = bp.take<char>(blk * es);
   w.map = bp.take<int>(64);
+  w.fused = bp.take<char>(fused_work_bytes(m.nf));
   w.dinv = bp.take<double>(m.nf);
   w.st = bp.take<double>((size_t)mr_state_count() * k);
   w.d1 = bp.take<double>(k);
@@ -312,6 +315,7 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
   ApplyArgs aa{};
   aa.v = v;
   aa.alpha = 1.0;
+  FusedWork fw = fused_layout(w.fused, nf);
   const int check_every = 8;
   // writes the compact solution columns back to Q and records per-column counters
   auto flush = [&](bool all_cols) -> fe_status {
@@ -331,15 +335,15 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
     aa.nv = k;
     aa.ld = k;
     aa.colshift = eps.data();
-    // y = (H - eps) (z / beta) ; y <- P y
+    // y = (H - eps) (z / beta)
     aa.X = Z;
     aa.Y = Y;
     aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
     if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
-    if ((st = project_out(Psi, k0, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
-    // alfa = v.(y - c1 r1)
-    if ((st = mr_dots<T>(Z, Y, R1, k, nf, w.d1, w.d2, w.dots, s)) != FE_OK) return st;
-    if ((st = mr_alfa(w.st, w.d1, w.d2, k, it == 1, s)) != FE_OK) return st;
+    // one sweep: G = Psi^T y, z.y, z.r1; alfa = v.(P y - c1 r1) = v.y - c1 v.r1 (v is orthogonal to Psi)
+    if ((st = minres_pass_a<T>(Psi, k0, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
+    if ((st = mr_alfa(w.st, fw.d1, fw.d2, k, it == 1, s)) != FE_OK) return st;
+    if ((st = project_with(Psi, k0, fw.G, Y, k, nf, f32, s)) != FE_OK) return st;  // y <- P y
     // r_new = y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; u <- P u
     if ((st = mr_resid_precond<T>(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new

@@ -423,14 +423,20 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
           const int gx = ex0 * P + xl, gy = ey0 * P + yl, j = j0 + jj;
           if (!node_ok(gx) || !node_ok(gy) || j >= nv) continue;
           const CT scale = (CT)(prm.kscale * prm.alpha) * (prm.colscale ? (CT)prm.colscale[j] : CT(1));
+          const long long base = node_index(gx, gy, 1) * ld + j;
+          const long long pstride = (long long)n1 * n1 * ld;
+          // Y may alias Z: read all of this column's Z values before the first store
+          CT zv[P];
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            const int gzo = ez * P + i;
+            zv[i] = (Z && node_ok(gzo)) ? Z[base + (long long)(gzo - 1) * pstride] : CT(0);
+          }
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             const int gzo = ez * P + i;
             if (!node_ok(gzo)) continue;
-            const long long idx = node_index(gx, gy, gzo) * ld + j;
-            CT out = scale * acc[c][i];
-            if (Z) out += (CT)prm.beta * Z[idx];
-            Y[idx] = out;
+            Y[base + (long long)(gzo - 1) * pstride] = scale * acc[c][i] + (CT)prm.beta * zv[i];
           }
         }
       }

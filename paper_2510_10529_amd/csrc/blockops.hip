@@ -379,6 +379,30 @@ fe_status colresid(const double* HX, const double* X, const double* lam, int ld,
   return FE_OK;
 }
 
+fe_status reduce_tiles(const double* partial, int nblk, int nx, int ny, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 3) / 4), dim3(256), 0, s, partial, nblk, 1, nx, ny, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+__global__ __launch_bounds__(256) void sum_strided_kernel(const double* __restrict__ partial, int nblk, int nv,
+                                                          int stride, int which, double* __restrict__ out) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += partial[((long long)b * stride + which) * nv + j];
+  s = wave_sum(s);
+  if (lane == 0) out[j] = s;
+}
+
+fe_status sum_columns_strided(const double* partial, int nblk, int nv, int stride, int which, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(sum_strided_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, stride, which, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, out);
   INVDFT_HIP(hipGetLastError());
@@ -449,6 +473,19 @@ fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f
   void* gw = w + (((size_t)k * nv * sizeof(double) + 255) / 256) * 256;
   fe_status st = gram(Psi, k, X, nv, N, k, nv, f32, G, gw, s);
   if (st != FE_OK) return st;
+  const unsigned grid = (unsigned)((N + 63) / 64);
+  if (f32)
+    hipLaunchKernelGGL(rotate_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(Psi), k,
+                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const float*>(X), static_cast<float*>(X), nv);
+  else
+    hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(Psi), k,
+                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const double*>(X), static_cast<double*>(X), nv);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status project_with(const void* Psi, int k, const double* G, void* X, int nv, int64_t N, bool f32, hipStream_t s) {
+  if (k > 64 || nv > 64) return fail(FE_EINVAL, "projection: blocks wider than 64 columns are not supported");
   const unsigned grid = (unsigned)((N + 63) / 64);
   if (f32)
     hipLaunchKernelGGL(rotate_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(Psi), k,

@@ -83,6 +83,11 @@ fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f
 // out[j] = sum_a (HX[a,j] - lam_j X[a,j])^2 (lam on device); work: coldot_work_bytes.
 fe_status colresid(const double* HX, const double* X, const double* lam, int ld, int64_t N, int nv, double* out,
                    void* work, hipStream_t s);
+// out (nx x ny) = fixed-order sum of nblk 64 x 64 partial tiles (nx, ny <= 64).
+fe_status reduce_tiles(const double* partial, int nblk, int nx, int ny, double* out, hipStream_t s);
+// out[j] = sum_b partial[(b * stride + which) * nv + j] (deterministic).
+fe_status sum_columns_strided(const double* partial, int nblk, int nv, int stride, int which, double* out,
+                              hipStream_t s);
 // out[j] = sum_b partial[b * nv + j] in block order (deterministic).
 fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s);
 // Scalar dot product of two FP64 vectors (device result).
@@ -100,6 +105,8 @@ fe_status fill(double* y, double val, int64_t n, hipStream_t s);
 size_t project_work_bytes(int64_t N, int k, int nv);
 // f32: Psi and X are float blocks (products accumulated in FP64).
 fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s);
+// X <- X - Psi G with a given G (k x nv, FP64 device).
+fe_status project_with(const void* Psi, int k, const double* G, void* X, int nv, int64_t N, bool f32, hipStream_t s);
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s);
 fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s);
 

@@ -21,6 +21,8 @@ int mr_state_iters();
 int mr_state_relres();
 int mr_state_active();
 int mr_state_invbeta();
+int mr_state_c1();
+int mr_state_c2();
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s);
 size_t mr_dots_work_bytes(int64_t nf, int k);
 template <typename T>

@@ -404,6 +404,8 @@ int mr_state_iters() { return S_ITERS; }
 int mr_state_relres() { return S_RELRES; }
 int mr_state_active() { return S_ACTIVE; }
 int mr_state_invbeta() { return S_INVBETA; }
+int mr_state_c1() { return S_C1; }
+int mr_state_c2() { return S_C2; }
 
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
   hipLaunchKernelGGL(mr_init_kernel<double>, dim3(1), dim3(256), 0, s, st, dot_r_z, k);
