@@ -235,7 +235,7 @@ struct MRWork {
   void* Qw;                              // compacted solution block
   int* map;                              // column map of a compaction (device)
   void* fused;                           // partial sums of the fused passes
-  double *dinv, *st, *d1, *d2, *bnorm, *dots, *pw;
+  double *dinv, *st, *d1, *d2, *bnorm, *pw;
   // FP32 refinement extras
   float* Psif;    // FP32 copy of Psi
   double *R64, *Y64;
@@ -259,7 +259,6 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
   w.d1 = bp.take<double>(k);
   w.d2 = bp.take<double>(k);
   w.bnorm = bp.take<double>(k);
-  w.dots = bp.take<double>(mr_dots_work_bytes(m.nf, k) / sizeof(double) + 1);
   w.pw = bp.take<double>(std::max(project_work_bytes(m.nf, k, k), coldot_work_bytes(m.nf, k)) / sizeof(double) + 1);
   if (prec != FE_F64) {
     w.X = bp.take<char>(blk * es);
@@ -343,14 +342,12 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
     // one sweep: G = Psi^T y, z.y, z.r1; alfa = v.(P y - c1 r1) = v.y - c1 v.r1 (v is orthogonal to Psi)
     if ((st = minres_pass_a<T>(Psi, k0, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
     if ((st = mr_alfa(w.st, fw.d1, fw.d2, k, it == 1, s)) != FE_OK) return st;
-    if ((st = project_with(Psi, k0, fw.G, Y, k, nf, f32, s)) != FE_OK) return st;  // y <- P y
-    // r_new = y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; u <- P u
-    if ((st = mr_resid_precond<T>(Y, R1, R2, w.st, w.dinv, k, nf, s)) != FE_OK) return st;
+    // r_new = P y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; G2 = Psi^T u ; beta^2 = r_new.u
+    if ((st = minres_pass_b<T>(Psi, k0, Y, R1, R2, w.st, w.dinv, k, nf, fw, s)) != FE_OK) return st;
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
-    if ((st = project_out(Psi, k0, Y, k, nf, f32, w.pw, s)) != FE_OK) return st;
-    if ((st = coldot(R2, Y, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
-    if ((st = mr_givens(w.st, w.d1, k, tol, s)) != FE_OK) return st;
-    if ((st = mr_update<T>(Z, Wb, Wa, Qw, w.st, k, nf, s)) != FE_OK) return st;
+    if ((st = mr_givens(w.st, fw.d, k, tol, s)) != FE_OK) return st;
+    // z_new = P u (into Y) ; w and q updates with the new rotation
+    if ((st = minres_pass_c<T>(Psi, k0, Y, Z, Wb, Wa, Qw, w.st, k, nf, fw, s)) != FE_OK) return st;
     std::swap(Wa, Wb);
     std::swap(Z, Y);  // Y now holds the previous z: free until the next apply
     if (it % check_every == 0 || it == maxit) {
@@ -751,6 +748,8 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
                         void* work, void* stream) {
   if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
   if (!v || !Psi || !eps_h || !B || !Q || !work) return fail(FE_EINVAL, "adjoint_solve: NULL argument");
+  if (!aligned16(Psi) || !aligned16(B) || !aligned16(Q) || !aligned16(work))
+    return fail(FE_EINVAL, "adjoint_solve: Psi, B, Q and work must be 16-byte aligned");
   if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "adjoint_solve: nocc must be in [1, 64]");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve: tol > 0 and maxit >= 1 required");
   if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "adjoint_solve: unsupported precision");

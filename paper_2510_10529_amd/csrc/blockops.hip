@@ -484,18 +484,6 @@ fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f
   return FE_OK;
 }
 
-fe_status project_with(const void* Psi, int k, const double* G, void* X, int nv, int64_t N, bool f32, hipStream_t s) {
-  if (k > 64 || nv > 64) return fail(FE_EINVAL, "projection: blocks wider than 64 columns are not supported");
-  const unsigned grid = (unsigned)((N + 63) / 64);
-  if (f32)
-    hipLaunchKernelGGL(rotate_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(Psi), k,
-                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const float*>(X), static_cast<float*>(X), nv);
-  else
-    hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(Psi), k,
-                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const double*>(X), static_cast<double*>(X), nv);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3(stream_grid(n)), dim3(256), 0, s, y, val, (long long)n);

@@ -106,7 +106,6 @@ size_t project_work_bytes(int64_t N, int k, int nv);
 // f32: Psi and X are float blocks (products accumulated in FP64).
 fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s);
 // X <- X - Psi G with a given G (k x nv, FP64 device).
-fe_status project_with(const void* Psi, int k, const double* G, void* X, int nv, int64_t N, bool f32, hipStream_t s);
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s);
 fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s);
 

@@ -16,26 +16,21 @@ fe_status k_rhs(const Mesh& m, const double* Psi, int nocc, const double* occ_h,
 fe_status k_grad(const Mesh& m, const double* Psi, const double* Q, int nocc, const double* rho_d, double tau,
                  double* g, hipStream_t s);
 
+// per-column scalar state (struct of arrays, each of length k)
+enum MrState {
+  S_BETA = 0, S_OLDB, S_DBAR, S_EPSLN, S_PHIBAR, S_BETA1, S_CS, S_SN, S_ALFA, S_C1, S_C2,
+  S_INVBETA, S_INVBETA_OLD, S_OLDEPS, S_DELTA, S_INVGAMMA, S_PHI, S_ACTIVE, S_ITERS, S_RELRES, S_D1, S_D2,
+  S_COUNT
+};
+
 int mr_state_count();
 int mr_state_iters();
 int mr_state_relres();
 int mr_state_active();
 int mr_state_invbeta();
-int mr_state_c1();
-int mr_state_c2();
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s);
-size_t mr_dots_work_bytes(int64_t nf, int k);
-template <typename T>
-fe_status mr_dots(const T* z, const T* y, const T* r1, int k, int64_t nf, double* d1, double* d2,
-                  double* partial, hipStream_t s);
 fe_status mr_alfa(double* st, const double* d1, const double* d2, int k, bool first, hipStream_t s);
 fe_status mr_givens(double* st, const double* dot_r_z, int k, double tol, hipStream_t s);
-template <typename T>
-fe_status mr_resid_precond(T* y, T* r1, const T* r2, const double* st, const double* dinv, int k,
-                           int64_t nf, hipStream_t s);
-template <typename T>
-fe_status mr_update(const T* zold, T* w1, const T* w2, T* x, const double* st, int k, int64_t nf,
-                    hipStream_t s);
 template <typename T>
 fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hipStream_t s);
 fe_status k_add_f32(const float* d, double* q, int64_t total, hipStream_t s);

@@ -120,12 +120,6 @@ __global__ void grad_kernel(const double* __restrict__ Psi, const double* __rest
 }
 
 // ------------------------------------------------------------------ MINRES
-// per-column scalar state (struct of arrays, each of length k)
-enum {
-  S_BETA = 0, S_OLDB, S_DBAR, S_EPSLN, S_PHIBAR, S_BETA1, S_CS, S_SN, S_ALFA, S_C1, S_C2,
-  S_INVBETA, S_INVBETA_OLD, S_OLDEPS, S_DELTA, S_INVGAMMA, S_PHI, S_ACTIVE, S_ITERS, S_RELRES, S_D1, S_D2,
-  S_COUNT
-};
 
 template <typename T>
 __global__ void mr_init_kernel(double* __restrict__ st, const double* __restrict__ dot_r_z, int k) {
@@ -215,65 +209,8 @@ __global__ void mr_givens_kernel(double* __restrict__ st, const double* __restri
   if (rel <= tol || beta == 0.0) s[S_ACTIVE * k + j] = 0.0;
 }
 
-// d1 = z.y and d2 = z.r1 column-wise partials (two dots in one pass)
-template <typename T>
-__global__ __launch_bounds__(256) void mr_dots_kernel(const T* __restrict__ z, const T* __restrict__ y,
-                                                      const T* __restrict__ r1, int k, long long nf,
-                                                      long long per, double* __restrict__ p1,
-                                                      double* __restrict__ p2) {
-  __shared__ double red1[256], red2[256];
-  const long long b0 = (long long)blockIdx.x * per;
-  const long long b1 = min(nf, b0 + per);
-  const int j = threadIdx.x % 64;
-  const int sub = threadIdx.x / 64;
-  double s1 = 0.0, s2 = 0.0;
-  if (j < k)
-    for (long long a = b0 + sub; a < b1; a += 4) {
-      const double zz = (double)z[a * k + j];
-      s1 += zz * (double)y[a * k + j];
-      s2 += zz * (double)r1[a * k + j];
-    }
-  red1[threadIdx.x] = s1;
-  red2[threadIdx.x] = s2;
-  __syncthreads();
-  if (threadIdx.x < 64 && j < k) {
-    p1[(long long)blockIdx.x * k + j] = ((red1[j] + red1[j + 64]) + red1[j + 128]) + red1[j + 192];
-    p2[(long long)blockIdx.x * k + j] = ((red2[j] + red2[j + 64]) + red2[j + 128]) + red2[j + 192];
-  }
-}
 
-// rnew = y - c1 r1 - c2 r2 (stored over r1) ; u = rnew / D (stored over y)
-template <typename T>
-__global__ void mr_resid_precond_kernel(T* __restrict__ y, T* __restrict__ r1,
-                                        const T* __restrict__ r2, const double* __restrict__ st,
-                                        const double* __restrict__ dinv, int k, long long nf) {
-  const long long total = nf * k;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(e % k);
-    const long long a = e / k;
-    if (!(st[S_ACTIVE * k + j] > 0.0)) continue;
-    const double rn = (double)y[e] - st[S_C1 * k + j] * (double)r1[e] - st[S_C2 * k + j] * (double)r2[e];
-    r1[e] = (T)rn;
-    y[e] = (T)(rn * dinv[a]);
-  }
-}
 
-// w_new = (z_old / beta_old - oldeps w1 - delta w2) / gamma ; x += phi w_new  (w_new stored over w1)
-template <typename T>
-__global__ void mr_update_kernel(const T* __restrict__ zold, T* __restrict__ w1,
-                                 const T* __restrict__ w2, T* __restrict__ x,
-                                 const double* __restrict__ st, int k, long long nf) {
-  const long long total = nf * k;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(e % k);
-    const double ig = st[S_INVGAMMA * k + j];
-    if (ig == 0.0) continue;  // frozen column (converged before this step)
-    const double wn = ((double)zold[e] * st[S_INVBETA_OLD * k + j] - st[S_OLDEPS * k + j] * (double)w1[e] -
-                       st[S_DELTA * k + j] * (double)w2[e]) * ig;
-    w1[e] = (T)wn;
-    x[e] = (T)((double)x[e] + st[S_PHI * k + j] * wn);
-  }
-}
 
 __global__ void dinv_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
                             double* __restrict__ dinv) {
@@ -404,8 +341,6 @@ int mr_state_iters() { return S_ITERS; }
 int mr_state_relres() { return S_RELRES; }
 int mr_state_active() { return S_ACTIVE; }
 int mr_state_invbeta() { return S_INVBETA; }
-int mr_state_c1() { return S_C1; }
-int mr_state_c2() { return S_C2; }
 
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
   hipLaunchKernelGGL(mr_init_kernel<double>, dim3(1), dim3(256), 0, s, st, dot_r_z, k);
@@ -413,22 +348,6 @@ fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
   return FE_OK;
 }
 
-template <typename T>
-fe_status mr_dots(const T* z, const T* y, const T* r1, int k, int64_t nf, double* d1, double* d2,
-                  double* partial, hipStream_t s) {
-  const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 1023) / 1024, 1024));
-  const long long per = (nf + nblk - 1) / nblk;
-  double* p1 = partial;
-  double* p2 = partial + (size_t)nblk * k;
-  hipLaunchKernelGGL(mr_dots_kernel<T>, dim3(nblk), dim3(256), 0, s, z, y, r1, k, (long long)nf, per, p1, p2);
-  INVDFT_HIP(hipGetLastError());
-  return sum_columns(p1, nblk, k, d1, s) == FE_OK ? sum_columns(p2, nblk, k, d2, s) : FE_EDEVICE;
-}
-
-size_t mr_dots_work_bytes(int64_t nf, int k) {
-  const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 1023) / 1024, 1024));
-  return (size_t)2 * nblk * k * sizeof(double);
-}
 
 fe_status mr_alfa(double* st, const double* d1, const double* d2, int k, bool first, hipStream_t s) {
   hipLaunchKernelGGL(mr_alfa_kernel, dim3(1), dim3(256), 0, s, st, d1, d2, k, first ? 1 : 0);
@@ -442,22 +361,7 @@ fe_status mr_givens(double* st, const double* dot_r_z, int k, double tol, hipStr
   return FE_OK;
 }
 
-template <typename T>
-fe_status mr_resid_precond(T* y, T* r1, const T* r2, const double* st, const double* dinv, int k,
-                           int64_t nf, hipStream_t s) {
-  hipLaunchKernelGGL(mr_resid_precond_kernel<T>, dim3(grid_for(nf * k)), dim3(256), 0, s, y, r1, r2, st, dinv, k,
-                     (long long)nf);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
-template <typename T>
-fe_status mr_update(const T* zold, T* w1, const T* w2, T* x, const double* st, int k, int64_t nf,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(mr_update_kernel<T>, dim3(grid_for(nf * k)), dim3(256), 0, s, zold, w1, w2, x, st, k, (long long)nf);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
 template <typename T>
 fe_status k_precond(const T* x, const double* dinv, int k, int64_t nf, T* y, hipStream_t s) {
@@ -499,18 +403,6 @@ fe_status k_mask_cols(float* r, const double* rr, const double* bb, double tol, 
   return FE_OK;
 }
 
-template fe_status mr_dots<double>(const double*, const double*, const double*, int, int64_t, double*, double*,
-                                   double*, hipStream_t);
-template fe_status mr_dots<float>(const float*, const float*, const float*, int, int64_t, double*, double*, double*,
-                                  hipStream_t);
-template fe_status mr_resid_precond<double>(double*, double*, const double*, const double*, const double*, int,
-                                            int64_t, hipStream_t);
-template fe_status mr_resid_precond<float>(float*, float*, const float*, const double*, const double*, int, int64_t,
-                                           hipStream_t);
-template fe_status mr_update<double>(const double*, double*, const double*, double*, const double*, int, int64_t,
-                                     hipStream_t);
-template fe_status mr_update<float>(const float*, float*, const float*, float*, const double*, int, int64_t,
-                                    hipStream_t);
 template fe_status k_precond<double>(const double*, const double*, int, int64_t, double*, hipStream_t);
 template fe_status k_precond<float>(const float*, const double*, int, int64_t, float*, hipStream_t);
 
