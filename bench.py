@@ -4,9 +4,20 @@ A step is one gradient iteration of the inverse loop: the forward Chebyshev-
 filtered eigensolve (warm-started from the previous iterate's orbitals), the
 density/loss/adjoint right-hand side, the batched MINRES adjoint solve, the
 gradient (all behind the autograd Function), and the potential update. Two
-paths run the same steps: the plain FP64 GPU path and the mixed-precision path
-(FP32 filter and FP32 MINRES with FP64 refinement, orbitals recomputed in
-backward). `value` is the mixed path's gradient iterations per second.
+paths run the same steps to the same tolerances: the plain FP64 GPU path and
+the mixed-precision path (FP32 Chebyshev filter with FP64 Rayleigh-Ritz,
+reductions and adjoint; orbitals recomputed in backward instead of stored).
+`value` is the mixed path's gradient iterations per second.
+
+The roofline object is for the dominant kernel of the timed region, the
+operator apply in the precision that takes the most time: every launch is
+timed by HIP events on its own stream (fe_apply_timing), and its algorithmic
+bytes (X read once, Y written once, v read once) are divided by the summed
+duration. Its HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+this same command, scaled by what the counters read for fe_axpby over 2^27
+doubles (launched at start-up as the reference), stored under profiles/ with
+the hash of the kernel source they were taken on; it is null when the kernel
+source has changed since.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5]
 """
@@ -51,6 +62,29 @@ def apply_timing(api, mesh, v, nv, prec, reps=20):
     return ms, algo_bytes
 
 
+def kernel_source_hash():
+    """Hash of the operator kernel source: the stored counter readings belong to it."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_10529_amd", "csrc", "apply.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(prec, workload_name):
+    """HBM bytes per launch of ks_apply in prec on this workload, from the rocprofv3 counter
+    summary under profiles/ (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale, KiB per
+    dispatch), or None when there is none for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ks_apply_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    for line in open(path):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if f.get("workload") == workload_name and f.get("prec") == prec and f.get("src") == want:
+            return 1024.0 * (float(f["fetch_kib"]) * float(f["fetch_scale"]) +
+                             float(f["write_kib"]) * float(f["write_scale"]))
+    return None
+
+
 def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, step_len):
     import torch
     prob = inv.InverseProblem(mesh, v_fixed, rho_d, n_elec, X0, opts)
@@ -72,6 +106,7 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
         log(f"  warmup {w}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
     prob.stats = inv.Stats()
     torch.cuda.synchronize()
+    api.apply_timing(True)             # HIP events around every operator launch of the timed steps
     t0 = time.perf_counter()
     for k in range(steps):
         l, g = one_step(u)
@@ -80,7 +115,9 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
         log(f"  step {k}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    return elapsed, losses, grads[0], prob
+    api.apply_timing(False)
+    timing = {p: api.apply_timing_read(p) for p in ("f64", "f32")}
+    return elapsed, losses, grads[0], prob, timing
 
 
 def main():
@@ -120,16 +157,16 @@ def main():
     del xyz_h
     nocc, nv = wl.n_occ, wl.n_occ + wl.n_buf
     log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}")
+    # a plain streaming kernel of known size, the reference for scaling the HBM byte
+    # counters of profiled runs: fe_axpby over 2^27 doubles reads 2 GiB and writes 1 GiB
+    xa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    ya = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        api.axpby(1.0, xa, 1.0, ya)
+    torch.cuda.synchronize()
+    del xa, ya
     if args.apply_only:
         out = {}
-        # a plain streaming kernel of known size, for scaling the HBM byte counters:
-        # fe_axpby over 2^27 doubles reads 2 GiB and writes 1 GiB
-        xa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        ya = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        for _ in range(2):
-            api.axpby(1.0, xa, 1.0, ya)
-        torch.cuda.synchronize()
-        del xa, ya
         for prec, cols in (("f64", nocc), ("f32", nv)):
             ms, b = apply_timing(api, mesh, v_fixed, cols, prec, reps=args.reps)
             out[f"ks_apply_{prec}"] = {"columns": cols, "ms": ms, "algorithmic_bytes": b,
@@ -158,14 +195,17 @@ def main():
     common = dict(degree=wl.cheb_degree, tol_eig=1e-9, tol_adj=1e-10, maxpass=100, maxit_adj=20000)
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
-        "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f32", switch_tol=1e-4,
+        "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=1e-4,
                                    recompute=True),
     }
     for name in args.paths.split(","):
         log(f"path {name}")
-        el, losses, g0, prob = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name], args.steps,
-                                        args.warmup, step_len)
-        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats)
+        el, losses, g0, prob, timing = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name],
+                                                args.steps, args.warmup, step_len)
+        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats, timing=timing)
+        for p_, (n_, ms_, b_) in timing.items():
+            if n_:
+                log(f"  ks_apply {p_}: {n_} launches, {ms_:.1f} ms, {b_ / ms_ / 1e6:.0f} GB/s")
         log(f"path {name}: {args.steps / el:.4f} iters/s  forward {prob.stats.t_forward:.2f} s  "
             f"adjoint {prob.stats.t_adjoint:.2f} s")
         del prob
@@ -180,13 +220,23 @@ def main():
         out_extra = {"fp64_path_iters_per_s": ips64, "speedup_vs_fp64_path": ips / ips64,
                      "grad_rel_diff_mixed_vs_fp64": rel}
 
-    # roofline of the dominant kernel (ks_apply) with HIP events on the launch stream
+    # apply alone at the two fixed block widths (context; HIP events on the launch stream)
     ms32, b32 = apply_timing(api, mesh, v_fixed, nv, "f32")
     ms64, b64 = apply_timing(api, mesh, v_fixed, nocc, "f64")
     gbs32 = b32 / ms32 / 1e6
     gbs64 = b64 / ms64 / 1e6
     log(f"ks_apply f32 nv={nv}: {ms32:.3f} ms {gbs32:.0f} GB/s ; f64 nv={nocc}: {ms64:.3f} ms {gbs64:.0f} GB/s")
 
+    # dominant kernel of the head path's timed steps: the apply precision with the most time
+    tim = head["timing"]
+    dom = max(tim, key=lambda p: tim[p][1])
+    n_l, ms_l, b_l = tim[dom]
+    achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
+    traffic = read_traffic(dom, wl.name)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
+                "algorithmic_bytes_per_launch": b_l / n_l}
     st = head["stats"]
     applies = None
     cpu = None
@@ -230,10 +280,7 @@ def main():
         "ks_apply_ms_f32": ms32,
         "ks_apply_ms_f64": ms64,
         **out_extra,
-        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None},
-        "roofline_f64": {"bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs64 / HBM_PEAK_GBS, "traffic": None},
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -199,6 +199,23 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
 fe_status fe_dot(const double* x, const double* y, int64_t n, double* out_h, void* work, void* stream);
 fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_t n, void* stream);
 
+/* ------------------------------------------------------- apply timing ----
+ * Measurement aid for the operator apply (not part of the method): while
+ * enabled, every operator launch (ks_apply and the applies inside
+ * cheb_filter, ks_eigensolve and adjoint_solve) is bracketed by two HIP events
+ * on the stream it is launched on, so that its duration is measured without
+ * synchronising the caller.
+ * fe_apply_timing(enable): 1 starts a new measurement (clears the record),
+ *   0 stops recording (the record is kept). Host-side, process-wide; not
+ *   thread-safe while launches are in flight.
+ * fe_apply_timing_read(prec, launches, ms, bytes): waits for the recorded
+ *   events and returns, for launches in precision prec (FE_F64 or FE_F32),
+ *   their count, summed duration in milliseconds and summed algorithmic
+ *   bytes (2 N_f nv s + 8 N_f per launch, s = 8 or 4). Any output may be NULL.
+ * Errors: FE_EINVAL for another prec, FE_EDEVICE for a failed event call. */
+fe_status fe_apply_timing(int enable);
+fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

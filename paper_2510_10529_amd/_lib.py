@@ -41,6 +41,8 @@ SIGNATURES = {
     "loss_grad": (C.c_int, [vp, vp, dp, C.c_int, vp, vp, C.c_double, vp, vp, vp, dp, vp, vp]),
     "fe_dot": (C.c_int, [vp, vp, C.c_int64, dp, vp, vp]),
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),
+    "fe_apply_timing": (C.c_int, [C.c_int]),
+    "fe_apply_timing_read": (C.c_int, [C.c_int, i64p, dp, dp]),
 }
 
 _lib = None

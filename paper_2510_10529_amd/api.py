@@ -194,3 +194,15 @@ def dot(x, y, work=None) -> float:
 def axpby(alpha: float, x, beta: float, y):
     L.check(L.load().fe_axpby(float(alpha), _ptr(x), float(beta), _ptr(y), x.numel(), _stream()), "fe_axpby")
     return y
+
+
+def apply_timing(enable: bool):
+    """Start (True: clears the record) or stop recording HIP-event timings of every operator apply."""
+    L.check(L.load().fe_apply_timing(1 if enable else 0), "fe_apply_timing")
+
+
+def apply_timing_read(prec: str = "f64"):
+    """(launches, total ms, total algorithmic bytes) of the recorded applies in precision prec."""
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    L.check(L.load().fe_apply_timing_read(PREC[prec], C.byref(n), C.byref(ms), C.byref(b)), "fe_apply_timing_read")
+    return n.value, ms.value, b.value

@@ -67,6 +67,8 @@ struct ApplyArgs {
   const double* d_colscale;   // device array (nv) or nullptr: output column j scaled by it
 };
 fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
+fe_status apply_timing(int enable);
+fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes);
 
 // Block operations (FP64 reductions; T = double or float storage).
 // Gram: out (nx x ny, row-major, FP64 device) = X^T Y over the first N rows.

@@ -67,6 +67,13 @@ def test_argument_checks_without_gpu():
     assert lib.fe_mesh_destroy(null) == _lib.FE_OK
     out = C.c_double()
     assert lib.fe_dot(None, None, 10, C.byref(out), None, None) == _lib.FE_EINVAL
+    # apply timing: an empty record reads back as zero launches, a bad precision is rejected
+    n, ms, b = C.c_int64(7), C.c_double(1.0), C.c_double(1.0)
+    assert lib.fe_apply_timing(1) == _lib.FE_OK
+    assert lib.fe_apply_timing_read(_lib.FE_F64, C.byref(n), C.byref(ms), C.byref(b)) == _lib.FE_OK
+    assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
+    assert lib.fe_apply_timing(0) == _lib.FE_OK
+    assert lib.fe_apply_timing_read(_lib.FE_BF16, None, None, None) == _lib.FE_EINVAL
 
 
 def test_status_exceptions_carry_message():
