@@ -213,6 +213,44 @@ def hamiltonian_apply(mesh: Mesh3D, v: np.ndarray, X: np.ndarray) -> np.ndarray:
     return kinetic_apply(mesh, X) + vx
 
 
+def hamiltonian_rows(mesh: Mesh3D, v: np.ndarray, X: np.ndarray, rows, shift=None) -> np.ndarray:
+    """Selected rows of (H~ - diag(shift)) X, each from its own definition (Eq. 19):
+
+        (K~ X)_a = sum_b [Ks(ax,bx) Ms(ay,by) Ms(az,bz) + Ms(ax,bx) Ks(ay,by) Ms(az,bz)
+                          + Ms(ax,bx) Ms(ay,by) Ks(az,bz)] X_b,
+
+    with Ks, Ms the W1^{-1/2}-scaled assembled 1-D stiffness and consistent mass, and
+    (H~ X)_a = (K~ X)_a / 2 + v_a X_a. Only the nodes b inside the 1-D bands of a enter,
+    so a row costs O((2p+1)^3 nv) whatever the mesh size: this is how large meshes are
+    checked on sampled outputs. rows: free-node indices; shift: nv per-column shifts.
+    """
+    m = mesh.m1
+    n1 = mesh.n1
+    s = 1.0 / np.sqrt(m.W1)
+    Ks = s[:, None] * m.K1 * s[None, :]
+    Ms = s[:, None] * m.Mc * s[None, :]
+    X = np.asarray(X)
+    nv = X.shape[1]
+    T = X.reshape(n1, n1, n1, nv)                    # [z, y, x, j], a view
+    rows = np.asarray(rows, dtype=np.int64)
+    out = np.empty((rows.size, nv))
+    for r, a in enumerate(rows):
+        ax, ay, az = a % n1, (a // n1) % n1, a // (n1 * n1)
+        band = [np.nonzero((Ks[c] != 0) | (Ms[c] != 0))[0] for c in (ax, ay, az)]
+        bx, by, bz = band
+        blk = T[np.ix_(bz, by, bx)].astype(np.float64)    # (nz, ny, nx, nv)
+        kx, mx = Ks[ax, bx], Ms[ax, bx]
+        ky, my = Ks[ay, by], Ms[ay, by]
+        kz, mz = Ks[az, bz], Ms[az, bz]
+        kin = (np.einsum("z,y,x,zyxj->j", mz, my, kx, blk) + np.einsum("z,y,x,zyxj->j", mz, ky, mx, blk)
+               + np.einsum("z,y,x,zyxj->j", kz, my, mx, blk))
+        xa = T[az, ay, ax].astype(np.float64)
+        out[r] = 0.5 * kin + v[a] * xa
+        if shift is not None:
+            out[r] -= np.asarray(shift, dtype=np.float64) * xa
+    return out
+
+
 def kinetic_diag(mesh: Mesh3D) -> np.ndarray:
     """Diagonal of K~/2: the preconditioner of Sec. 3.2.2 (inverse diagonal of the
     kinetic, i.e. negative-Laplacian, part)."""

@@ -112,6 +112,24 @@ def test_symmetry_and_two_applies_agree():
     np.testing.assert_allclose(fe.kinetic_diag(m), fe.kinetic_csr(m).diagonal(), rtol=1e-13)
 
 
+@pytest.mark.parametrize("p,n,L", [(4, 3, 4.0), (5, 2, 3.0), (2, 4, 5.0)])
+def test_sampled_rows_match_assembled_operator(p, n, L):
+    """Row-by-row evaluation (used to check full-size runs on sampled nodes) against the
+    assembled CSR operator and the Kronecker apply, on every row of small meshes."""
+    wl = workload(2, p=p, n=n, half_width=L)
+    m = fe.mesh3d(wl.p, wl.n, wl.half_width)
+    v = wl.v_fixed(m.coords()) + wl.v_xc_target(m.coords())
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((m.n_free, 4))
+    shift = rng.standard_normal(4)
+    ref = fe.hamiltonian_csr(m, v) @ X - X * shift[None, :]
+    rows = np.arange(m.n_free)
+    got = fe.hamiltonian_rows(m, v, X, rows, shift=shift)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    got2 = fe.hamiltonian_rows(m, v, X, rows[::7])
+    np.testing.assert_allclose(got2, fe.hamiltonian_apply(m, v, X)[::7], rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 # ------------------------------------------------------------ P6 Fried bound
 @pytest.mark.parametrize("p,h", [(5, 0.8), (4, 0.75), (2, 4.0 / 3.0)])
 @pytest.mark.parametrize("n", [2, 3])
