@@ -170,8 +170,10 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
  *   host doubles, B: right-hand sides (N_f x nocc, orthogonal to Psi), Q: out.
  *   iters_h (nocc ints) and relres_h (nocc doubles: true ||b - A q|| / ||b||,
  *   nullable) are filled on return.
- * prec: FE_F64, or FE_F32 = FP32 inner MINRES with FP64 iterative refinement
- * (residuals and updates of Q in FP64).
+ * prec: FE_F64, or FE_F32 = FP32 inner MINRES (relative tolerance
+ * max(tol, 1e-4)) with FP64 iterative refinement (residuals and updates of Q in
+ * FP64). nocc <= 64. Columns that have converged are dropped from the batch.
+ * Psi, B, Q and work must be 16-byte aligned (FE_EINVAL otherwise).
  * Returns FE_ENOCONV when some column did not reach tol in maxit iterations.
  * work: fe_workspace_bytes(FE_OP_ADJOINT_SOLVE, nocc, prec). Synchronises. */
 fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h,

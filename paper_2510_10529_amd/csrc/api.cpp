@@ -772,8 +772,7 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
   } else {
     // FP32 MINRES inner solves with FP64 iterative refinement: q += d, (H - eps) d = r in FP32,
     // r = b - (H - eps) q in FP64, until every column reaches tol.
-    double tol_inner = std::max(tol, 1e-4);
-    if (const char* e = std::getenv("INVDFT_INNER_TOL")) tol_inner = std::max(tol, std::atof(e));  // experiments
+    const double tol_inner = std::max(tol, 1e-4);
     if ((st = cast_block_to_f32(Psi, w.Psif, blk, s)) != FE_OK) return st;
     if ((st = fill(Q, 0.0, blk, s)) != FE_OK) return st;
     if ((st = copy_bytes(B, w.R64, blk * sizeof(double), s)) != FE_OK) return st;
