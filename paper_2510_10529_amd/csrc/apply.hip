@@ -52,22 +52,13 @@ struct KParams {
 };
 
 // Tile shape per order: BEX x BEY cells per workgroup in x and y (a z-range of
-// cells is marched). Small tiles keep LDS near 24 KB and registers near 110, so
-// about four workgroups share a CU and overlap each other's barriers and loads.
-#ifndef KS_APPLY_MIN_WAVES
-#define KS_APPLY_MIN_WAVES 1
-#endif
-#ifndef KS_APPLY_BEY5
-#define KS_APPLY_BEY5 1
-#endif
-#ifndef KS_APPLY_FP64_M_SCALAR
-#define KS_APPLY_FP64_M_SCALAR 1
-#endif
+// cells is marched), chosen by measurement. Larger tiles read less halo per owned
+// node but cost LDS and registers: at P = 5 in FP64 the 2 x 2 tile takes about
+// 62 KB of LDS and 225 VGPRs, two workgroups per CU.
 template <int P, typename T>
 struct TileShape {
   static constexpr int BEX = (P == 1) ? 4 : (P == 2) ? 4 : (P <= 5) ? 2 : 1;
-  // at P = 5 the FP64 kernel is fastest with 2 x 2 cells, the FP32 one with 2 x 1
-  static constexpr int BEY = (P == 1) ? 4 : (P == 2) ? 2 : (P <= 4) ? 2 : (P == 5) ? (sizeof(T) == 8 ? 2 : KS_APPLY_BEY5) : 1;
+  static constexpr int BEY = (P == 1) ? 4 : (P <= 5) ? 2 : 1;
 };
 
 // Distinct entries of a symmetric, centrosymmetric (P+1)x(P+1) matrix: slot of (i, k).
@@ -147,7 +138,7 @@ __device__ __forceinline__ void z_accumulate(int k, const CT (&cM)[NU], const CT
 }
 
 template <typename T, int P, int J, int NT>
-__global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const KParams prm) {
+__global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   using CT = T;  // compute type = storage type (FP64 or FP32)
   constexpr int P1 = P + 1;
   constexpr int BEX = TileShape<P, T>::BEX, BEY = TileShape<P, T>::BEY;
@@ -219,7 +210,7 @@ __global__ __launch_bounds__(NT, KS_APPLY_MIN_WAVES) void ks_apply_kernel(const 
     if constexpr (sizeof(CT) == sizeof(double)) {
       // split: mass entries stay scalar (uniform), stiffness entries in vector registers
       const int r = Canon<P>::map.rep_of[q];
-      cM[q] = KS_APPLY_FP64_M_SCALAR ? (CT)ref::Table<P>::value.mt[r / (P + 1)][r % (P + 1)] : sTab[0][q];
+      cM[q] = (CT)ref::Table<P>::value.mt[r / (P + 1)][r % (P + 1)];
       cK[q] = sTab[1][q];
     } else {
       const int r = Canon<P>::map.rep_of[q];

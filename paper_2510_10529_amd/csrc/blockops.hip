@@ -379,35 +379,9 @@ fe_status colresid(const double* HX, const double* X, const double* lam, int ld,
   return FE_OK;
 }
 
-fe_status reduce_tiles(const double* partial, int nblk, int nx, int ny, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 3) / 4), dim3(256), 0, s, partial, nblk, 1, nx, ny, out);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
-__global__ __launch_bounds__(256) void sum_strided_kernel(const double* __restrict__ partial, int nblk, int nv,
-                                                          int stride, int which, double* __restrict__ out) {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= nv) return;
-  double s = 0.0;
-  for (int b = lane; b < nblk; b += 64) s += partial[((long long)b * stride + which) * nv + j];
-  s = wave_sum(s);
-  if (lane == 0) out[j] = s;
-}
 
-fe_status sum_columns_strided(const double* partial, int nblk, int nv, int stride, int which, double* out,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(sum_strided_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, stride, which, out);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
-fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, partial, nblk, nv, out);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
-}
 
 fe_status dot1(const double* x, const double* y, int64_t n, double* out, void* work, hipStream_t s) {
   const int nblk = (int)std::max<long long>(1, std::min<long long>((n + 4095) / 4096, 1024));
@@ -431,10 +405,6 @@ fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t 
   return FE_OK;
 }
 
-fe_status copy_block(const double* src, double* dst, int64_t count, hipStream_t s) {
-  INVDFT_HIP(hipMemcpyAsync(dst, src, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, s));
-  return FE_OK;
-}
 
 fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL((cast_kernel<double, float>), dim3(stream_grid(count)), dim3(256), 0, s, src, dst,

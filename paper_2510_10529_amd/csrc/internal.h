@@ -85,19 +85,11 @@ fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f
 // out[j] = sum_a (HX[a,j] - lam_j X[a,j])^2 (lam on device); work: coldot_work_bytes.
 fe_status colresid(const double* HX, const double* X, const double* lam, int ld, int64_t N, int nv, double* out,
                    void* work, hipStream_t s);
-// out (nx x ny) = fixed-order sum of nblk 64 x 64 partial tiles (nx, ny <= 64).
-fe_status reduce_tiles(const double* partial, int nblk, int nx, int ny, double* out, hipStream_t s);
-// out[j] = sum_b partial[(b * stride + which) * nv + j] (deterministic).
-fe_status sum_columns_strided(const double* partial, int nblk, int nv, int stride, int which, double* out,
-                              hipStream_t s);
-// out[j] = sum_b partial[b * nv + j] in block order (deterministic).
-fe_status sum_columns(const double* partial, int nblk, int nv, double* out, hipStream_t s);
 // Scalar dot product of two FP64 vectors (device result).
 fe_status dot1(const double* x, const double* y, int64_t n, double* out, void* work, hipStream_t s);
 fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t s);
 
 // Kernels used by the Krylov and loss/gradient code (defined in blockops.hip).
-fe_status copy_block(const double* src, double* dst, int64_t count, hipStream_t s);
 fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
 fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s);
 fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s);

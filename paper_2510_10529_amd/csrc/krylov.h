@@ -25,7 +25,6 @@ enum MrState {
 
 int mr_state_count();
 int mr_state_iters();
-int mr_state_relres();
 int mr_state_active();
 int mr_state_invbeta();
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s);

@@ -338,7 +338,6 @@ fe_status k_grad(const Mesh& m, const double* Psi, const double* Q, int nocc, co
 // ----------------------------------------------------------------- MINRES
 int mr_state_count() { return S_COUNT; }
 int mr_state_iters() { return S_ITERS; }
-int mr_state_relres() { return S_RELRES; }
 int mr_state_active() { return S_ACTIVE; }
 int mr_state_invbeta() { return S_INVBETA; }
 
