@@ -77,3 +77,55 @@ def test_pin_catches_missing_weight(monkeypatch):
     assert abs(ks.electron_count(ks.density(fw.psi, occ, W), W) - wl.n_elec) < 1e-12
     monkeypatch.setattr(ks, "density", lambda psi, occ, W: psi[:, :occ.size] ** 2 @ occ)
     assert abs(ks.electron_count(ks.density(fw.psi, occ, W), W) - wl.n_elec) > 1e-3
+
+
+# ------------------------------------------------ finite temperature (Eqs. 7-9)
+def _thermal_fd_mismatch(kT=0.05):
+    from oracle import thermal as th
+    wl = workload(2, p=2, n=3, half_width=4.0)
+    m = fe.mesh3d(2, 3, 4.0)
+    X = m.coords()
+    vf, vs = wl.v_fixed(X), wl.v_xc_target(X)
+    rho_d = th.target_density(m, vf + vs, wl.n_elec, kT)
+    v = vf + 0.5 * np.sin(X[:, 0]) + 0.05
+    ev = th.evaluate(m, v, rho_d, wl.n_elec, kT)
+    d = np.random.default_rng(3).standard_normal(m.n_free)
+    fd = th.fd_directional(m, v, rho_d, wl.n_elec, kT, d, 1e-4)
+    return abs(ev.grad @ d - fd) / abs(fd)
+
+
+def test_thermal_pin_catches_dropped_eta(monkeypatch):
+    from oracle import thermal as th
+    assert _thermal_fd_mismatch() < 1e-5
+    monkeypatch.setattr(th, "eta", lambda *a: 0.0)
+    assert _thermal_fd_mismatch() > 1e-3
+
+
+def test_thermal_pin_catches_dropped_overlap_term(monkeypatch):
+    """P_k without its component along Psi_k (Eq. 8), as at zero temperature."""
+    from oracle import thermal as th
+    monkeypatch.setattr(th, "overlap", lambda S, dfde, et: np.zeros_like(S))
+    assert _thermal_fd_mismatch() > 1e-3
+
+
+def test_thermal_pin_catches_wrong_sign_in_overlap(monkeypatch):
+    from oracle import thermal as th
+    monkeypatch.setattr(th, "overlap", lambda S, dfde, et: dfde * (2.0 * S + et * np.eye(S.shape[0])))
+    assert _thermal_fd_mismatch() > 1e-3
+
+
+def test_thermal_check_catches_wrong_multiplier(monkeypatch):
+    """A slip in D_k + D_k^T leaves Eq. 7's right-hand side with a component along its
+    block; the oracle refuses it rather than letting the bordered solve hide it."""
+    from oracle import thermal as th
+    monkeypatch.setattr(th, "d_plus_dt", lambda S, fk: 2.0 * S * fk)
+    with pytest.raises(RuntimeError):
+        _thermal_fd_mismatch()
+
+
+def test_thermal_pin_catches_occupancy_without_spin_factor(monkeypatch):
+    """Occupancy f in [0, 1] while its derivative still carries the factor s = 2."""
+    from oracle import thermal as th
+    orig = th.occupancy
+    monkeypatch.setattr(th, "occupancy", lambda e, mu, kT, smax=2.0: orig(e, mu, kT, 1.0))
+    assert _thermal_fd_mismatch() > 1e-3
