@@ -64,7 +64,8 @@ typedef enum {
   FE_EDEVICE = 3,  /* HIP runtime error (message in fe_last_error) */
   FE_ENOCONV = 4,  /* iteration limit reached; outputs hold the last iterate */
   FE_ENOTPD = 5,   /* Cholesky of an overlap matrix failed; block left unchanged */
-  FE_EGAP = 6      /* no gap at the Fermi level: eps[nocc] - eps[nocc-1] < 1e-6 Ha */
+  FE_EGAP = 6,     /* no gap at the Fermi level: eps[nocc] - eps[nocc-1] < 1e-6 Ha */
+  FE_ESTATES = 7   /* too few states for the Fermi tail: the highest one passed is occupied */
 } fe_status;
 
 typedef enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 } fe_prec;
@@ -76,7 +77,8 @@ typedef enum {
   FE_OP_RAYLEIGH_RITZ = 2,
   FE_OP_ADJOINT_SOLVE = 3,
   FE_OP_LOSS_GRAD = 4,
-  FE_OP_EIGENSOLVE = 5
+  FE_OP_EIGENSOLVE = 5,
+  FE_OP_ALONG_PSI = 6
 } fe_op;
 
 /* ------------------------------------------------------------------ mesh --
@@ -104,7 +106,8 @@ fe_status fe_mesh_kinetic_diag(fe_mesh mesh, double* d, void* stream);
 fe_status fe_mesh_destroy(fe_mesh mesh);
 
 /* Bytes of device work buffer an operation needs for a block of nv columns
- * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD). 0 on bad input. */
+ * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD, nv = n for
+ * FE_OP_ALONG_PSI). 0 on bad input. */
 size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec);
 
 const char* fe_last_error(void);
@@ -193,6 +196,49 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
 fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc,
                     const double* rho_data, const double* Q, double tau_bc, double* rho, double* B,
                     double* grad, double* loss_h, void* work, void* stream);
+
+/* ----------------------------------------------------- fermi_occupations --
+ * Finite-temperature occupations (Eq. 4's Fermi-Dirac occupancy, Eq. 5):
+ *   f_i = smax / (1 + exp((eig_i - mu) / kT)), mu such that sum_i f_i = n_elec,
+ * found by bisection to the last bit (sum_i f_i increases with mu). smax is the
+ * occupancy of a full orbital: 2 for spin-restricted orbitals, 1 for the paper's
+ * per-orbital form. Host-only: no device work, no stream.
+ *   eig_h: n ascending host doubles (the lowest n eigenvalues of H~).
+ *   occ_h: out, n host doubles f_i. dfde_h (nullable): out, d f_i / d eig_i.
+ *   mu_h (nullable): out, mu. n_incl_h (nullable): out, the number of leading
+ *   states with f_i > occ_cut * smax, extended over Ritz values closer than
+ *   1e-6 Ha so that no degenerate group is split: the orbitals to pass on.
+ * Errors: FE_EINVAL (kT <= 0, smax <= 0, occ_cut outside [0, 1), n < 1,
+ * n_elec outside (0, smax n), eigenvalues not ascending); FE_ESTATES when the
+ * highest state passed holds more than occ_cut * smax (all outputs are written:
+ * compute more states). */
+fe_status fermi_occupations(const double* eig_h, int n, double n_elec, double kT, double smax,
+                            double occ_cut, double* occ_h, double* dfde_h, double* mu_h, int* n_incl_h);
+
+/* ----------------------------------------------------- adjoint_along_psi --
+ * The component of the adjoint functions along the included orbitals at
+ * finite temperature (Eqs. 8, 9 and the in-span part of Eq. 7), added to the
+ * MINRES solution Q of adjoint_solve (which is orthogonal to all n orbitals):
+ *   M = Psi^T diag(2 (rho - rho_data)) Psi                 (n x n, FP64 MFMA)
+ *   etabar = sum_i f'_i M_ii / sum_i f'_i                  (eta of Eq. 9 = -etabar)
+ *   C_ii = f'_i (M_ii - etabar),  C_ij = M_ij (f_i - f_j) / (eps_i - eps_j)
+ *   Q <- Q + Psi C
+ * with f_i, f'_i = d f_i / d eps_i from (mu, kT, smax) as in fermi_occupations
+ * (the divided difference is evaluated without cancellation and tends to f'_i
+ * as eps_j -> eps_i, so degenerate groups need no special treatment). Then
+ * loss_grad phase 2 with this Q gives the gradient of Eq. 10. Over each
+ * degenerate group the diagonal block of C is Eq. 8's overlap; between groups
+ * the coupling is split symmetrically, which changes the individual adjoint
+ * functions but not the gradient.
+ *   Psi: N_f x n (ld = n), n <= 64; eps_h: n host doubles; rho, rho_data: N_f;
+ *   Q: N_f x n (ld = n), in/out. eta_h (nullable): out, eta of Eq. 9.
+ *   C_h (nullable): out, n x n host doubles (row-major).
+ * Psi, Q and work must be 16-byte aligned. work: fe_workspace_bytes(
+ * FE_OP_ALONG_PSI, n). Synchronises the stream.
+ * Errors: FE_EINVAL (NULL or misaligned pointers, n outside [1, 64], kT <= 0). */
+fe_status adjoint_along_psi(fe_mesh mesh, const double* Psi, int n, const double* eps_h, double mu, double kT,
+                            double smax, const double* rho, const double* rho_data, double* Q, double* eta_h,
+                            double* C_h, void* work, void* stream);
 
 /* --------------------------------------------------------- block helpers --
  * Small FP64 vector kernels used by the host-side L-BFGS driver (Eq. 21):

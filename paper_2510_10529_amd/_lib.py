@@ -10,12 +10,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libinvdft.so")
 
-FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV, FE_ENOTPD, FE_EGAP = range(7)
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV, FE_ENOTPD, FE_EGAP, FE_ESTATES = range(8)
 FE_F64, FE_F32, FE_BF16 = 0, 1, 2
-FE_OP_KS_APPLY, FE_OP_CHEB_FILTER, FE_OP_RAYLEIGH_RITZ, FE_OP_ADJOINT_SOLVE, FE_OP_LOSS_GRAD, FE_OP_EIGENSOLVE = range(6)
+(FE_OP_KS_APPLY, FE_OP_CHEB_FILTER, FE_OP_RAYLEIGH_RITZ, FE_OP_ADJOINT_SOLVE, FE_OP_LOSS_GRAD, FE_OP_EIGENSOLVE,
+ FE_OP_ALONG_PSI) = range(7)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE", 4: "FE_ENOCONV",
-                5: "FE_ENOTPD", 6: "FE_EGAP"}
+                5: "FE_ENOTPD", 6: "FE_EGAP", 7: "FE_ESTATES"}
 
 vp = C.c_void_p
 dp = C.POINTER(C.c_double)
@@ -43,6 +44,10 @@ SIGNATURES = {
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),
     "fe_apply_timing": (C.c_int, [C.c_int]),
     "fe_apply_timing_read": (C.c_int, [C.c_int, i64p, dp, dp]),
+    "fermi_occupations": (C.c_int, [dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp,
+                                    ip]),
+    "adjoint_along_psi": (C.c_int, [vp, vp, C.c_int, dp, C.c_double, C.c_double, C.c_double, vp, vp, vp, dp,
+                                    dp, vp, vp]),
 }
 
 _lib = None

@@ -206,3 +206,40 @@ def apply_timing_read(prec: str = "f64"):
     n, ms, b = C.c_int64(), C.c_double(), C.c_double()
     L.check(L.load().fe_apply_timing_read(PREC[prec], C.byref(n), C.byref(ms), C.byref(b)), "fe_apply_timing_read")
     return n.value, ms.value, b.value
+
+
+@dataclass
+class Occupations:
+    occ: list
+    dfde: list
+    mu: float
+    n_incl: int
+    status: int
+
+
+def fermi_occupations(eig, n_elec: float, kT: float, smax: float = 2.0, occ_cut: float = 1e-12,
+                      allow=()) -> Occupations:
+    """Fermi-Dirac occupations of the given eigenvalues and mu from the electron count (host call)."""
+    n = len(eig)
+    occ = (C.c_double * n)()
+    dfde = (C.c_double * n)()
+    mu = C.c_double()
+    ninc = C.c_int()
+    st = L.load().fermi_occupations(_host_doubles(eig), n, float(n_elec), float(kT), float(smax), float(occ_cut),
+                                    occ, dfde, C.byref(mu), C.byref(ninc))
+    L.check(st, "fermi_occupations", allow=allow)
+    return Occupations(list(occ), list(dfde), mu.value, ninc.value, st)
+
+
+def adjoint_along_psi(mesh: Mesh, Psi, eps, mu: float, kT: float, rho, rho_data, Q, smax: float = 2.0,
+                      work=None):
+    """Q <- Q + Psi C (the in-span part of the finite-temperature adjoint). Returns (eta, C as a list)."""
+    n = Psi.shape[1]
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_ALONG_PSI, n), Psi.device)
+    eta = C.c_double()
+    Ch = (C.c_double * (n * n))()
+    L.check(L.load().adjoint_along_psi(mesh.handle, _ptr(Psi), n, _host_doubles(eps), float(mu), float(kT),
+                                       float(smax), _ptr(rho), _ptr(rho_data), _ptr(Q), C.byref(eta), Ch,
+                                       _ptr(work), _stream()), "adjoint_along_psi")
+    return eta.value, list(Ch)

@@ -597,6 +597,7 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
       bp.take<double>(1025);
       bp.take<double>(project_work_bytes(m.nf, nv, nv) / sizeof(double) + 1);
       return bp.off;
+    case FE_OP_ALONG_PSI: return along_psi_work_bytes(m.nf, nv);
     default: return 0;
   }
 }

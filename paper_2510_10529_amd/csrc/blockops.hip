@@ -35,10 +35,13 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 constexpr int kGramThreads = 256;
 constexpr int kGramTile = 64;  // output tile edge handled by one workgroup (4 x 4 MFMA tiles)
 
-// partial[blk][i][j] (for this output tile) = sum over the block's rows of X[r][i] Y[r][j].
-template <typename T>
+// partial[blk][i][j] (for this output tile) = sum over the block's rows of X[r][i] Y[r][j], or with
+// WEIGHTED of X[r][i] (wa[r] - wb[r]) Y[r][j] (a diagonal weight that keeps a symmetric product symmetric).
+template <typename T, bool WEIGHTED>
 __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(const T* __restrict__ X, int ldx,
                                                                     const T* __restrict__ Y, int ldy,
+                                                                    const double* __restrict__ wa,
+                                                                    const double* __restrict__ wb,
                                                                     long long N, int nx, int ny,
                                                                     long long rows_per_blk, int sym,
                                                                     double* __restrict__ partial) {
@@ -64,11 +67,14 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(const T* __r
     const long long r = r0 + lk;
     const bool rok = r < r_end;
     double av[4], bv[4];
+    double wr = 1.0;
+    if constexpr (WEIGHTED) wr = rok ? wa[r] - wb[r] : 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int ci = i0 + 16 * t + li;
       const int cj = j0 + 16 * t + li;
       av[t] = (rok && ci < nx) ? ld_d(X + r * ldx + ci) : 0.0;
+      if constexpr (WEIGHTED) av[t] *= wr;
       bv[t] = (rok && cj < ny) ? ld_d(Y + r * ldy + cj) : 0.0;
     }
 #pragma unroll
@@ -323,14 +329,43 @@ fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx
   double* partial = static_cast<double*>(work);
   dim3 grid(nblk, tiles_i * tiles_j);
   if (f32)
-    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(kGramThreads), 0, s, static_cast<const float*>(X), ldx,
-                       static_cast<const float*>(Y), ldy, (long long)N, nx, ny, rpb, sym, partial);
+    hipLaunchKernelGGL((gram_partial_kernel<float, false>), grid, dim3(kGramThreads), 0, s,
+                       static_cast<const float*>(X), ldx, static_cast<const float*>(Y), ldy, nullptr, nullptr,
+                       (long long)N, nx, ny, rpb, sym, partial);
   else
-    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(kGramThreads), 0, s, static_cast<const double*>(X),
-                       ldx, static_cast<const double*>(Y), ldy, (long long)N, nx, ny, rpb, sym, partial);
+    hipLaunchKernelGGL((gram_partial_kernel<double, false>), grid, dim3(kGramThreads), 0, s,
+                       static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, nullptr, nullptr,
+                       (long long)N, nx, ny, rpb, sym, partial);
   INVDFT_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((nx * ny + 3) / 4), dim3(256), 0, s, partial, nblk,
                      tiles_i * tiles_j, nx, ny, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status gram_weighted(const double* X, int ld, const double* wa, const double* wb, int64_t N, int n, double* out,
+                        void* work, hipStream_t s) {
+  if (n <= 0) return FE_OK;
+  const int nblk = gram_blocks(N);
+  const int tiles = (n + kGramTile - 1) / kGramTile;
+  const long long rpb = (N + nblk - 1) / nblk;
+  double* partial = static_cast<double*>(work);
+  hipLaunchKernelGGL((gram_partial_kernel<double, true>), dim3(nblk, tiles * tiles), dim3(kGramThreads), 0, s, X, ld,
+                     X, ld, wa, wb, (long long)N, n, n, rpb, 1, partial);
+  INVDFT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((n * n + 3) / 4), dim3(256), 0, s, partial, nblk, tiles * tiles, n, n,
+                     out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* Y, int ldy,
+                     hipStream_t s) {
+  if (nin > 64 || nout > 64) return fail(FE_EINVAL, "rotate: blocks wider than 64 columns are not supported");
+  if (N <= 0) return FE_OK;
+  const unsigned grid = (unsigned)((N + 63) / 64);
+  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, 1.0, 1.0,
+                     (const double*)Y, Y, ldy);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

@@ -79,6 +79,13 @@ fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx
 fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* out,
                  int ldo, hipStream_t s);
 // Column-wise dot products d_j = sum_a X[a,j] Y[a,j] (FP64 result, device array nv).
+// out = X^T diag(wa - wb) X (n x n, X: N x n with leading dimension ld); work: gram_work_bytes(N, n, n).
+fe_status gram_weighted(const double* X, int ld, const double* wa, const double* wb, int64_t N, int n, double* out,
+                        void* work, hipStream_t s);
+size_t along_psi_work_bytes(int64_t N, int n);
+// Y += X C over N rows (X: N x nin, C: nin x nout row-major on the device, Y: N x nout).
+fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* Y, int ldy,
+                     hipStream_t s);
 size_t coldot_work_bytes(int64_t N, int nv);
 fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f32, double* out, void* work,
                  hipStream_t s);

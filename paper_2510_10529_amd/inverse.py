@@ -7,6 +7,11 @@ Backward: optionally recompute the orbitals (from the warm-start block, so they
 need not be kept between forward and backward), solve the adjoint equations by
 batched projected MINRES (Eq. 20) and form g_b = sum_i psi_{b,i} q_{b,i} (Eq. 22).
 
+Finite temperature (kT > 0): the occupations are Fermi-Dirac with mu from the
+electron count (Eqs. 4, 5); every orbital with f_i above a cut enters the density
+and the adjoint, and the adjoint functions gain their component along the included
+orbitals (Eqs. 8, 9) before the gradient of Eq. 10 is formed.
+
 Every operation on device vectors is a call into libinvdft.so; torch supplies the
 buffers and the stream.
 """
@@ -37,6 +42,19 @@ class SolverOptions:
     adaptive: bool = False           # t_eig = e_L2^2 / c_eig, t_ad = e_L2^2 / c_ad (Table 1 defaults)
     c_eig: float = 1e2
     c_ad: float = 1e5
+    kT: float = 0.0                  # k_B T in Ha; 0 = doubly occupied lowest N_e/2 orbitals
+    smax: float = 2.0                # occupancy of a full orbital (spin-restricted)
+    n_states: int = 0                # finite T: Ritz pairs to converge (0 = block width - 4)
+    occ_cut: float = 1e-12           # finite T: orbitals with f_i <= occ_cut * smax are left out
+
+
+@dataclass
+class OccState:
+    """Occupations of one forward solve: the first n orbitals enter."""
+    n: int
+    occ: list
+    eig: list
+    mu: float | None = None          # None at T = 0
 
 
 @dataclass
@@ -57,19 +75,27 @@ class InverseProblem:
         self.mesh = mesh
         self.v_fixed = v_fixed
         self.rho_data = rho_data
-        self.nocc = n_elec // 2
-        self.occ = [2.0] * self.nocc
+        self.n_elec = n_elec
         self.opts = opts or SolverOptions()
         self.nv = X0.shape[1]
+        o = self.opts
+        if o.kT > 0:
+            self.nconv = o.n_states or self.nv - 4     # Ritz pairs the eigensolver converges
+            if not 0 < self.nconv < self.nv:
+                raise ValueError("finite temperature needs 0 < n_states < block width")
+        else:
+            self.nconv = n_elec // 2
+        self.nocc = self.nconv                 # widest block of orbitals that can enter
+        self.state = OccState(n_elec // 2, [2.0] * (n_elec // 2), [])
         self.X = X0.clone()                    # FP64 warm-start block (Ritz vectors)
         self.v = torch.empty_like(v_fixed)
         self.eig = None
         self.stats = Stats()
         dev = X0.device
-        o = self.opts
         self.work_eig = api._work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, self.nv, o.filter_prec), dev)
         self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
         self.work_lg = api._work(mesh.workspace_bytes(L.FE_OP_LOSS_GRAD, self.nocc), dev)
+        self.work_ap = (api._work(mesh.workspace_bytes(L.FE_OP_ALONG_PSI, self.nocc), dev) if o.kT > 0 else None)
         self.last_loss = None
 
     # ------------------------------------------------------------------ pieces
@@ -87,32 +113,44 @@ class InverseProblem:
     def eigensolve(self, tol_eig):
         o = self.opts
         t0 = time.perf_counter()
-        r = api.ks_eigensolve(self.mesh, self.v, self.X, self.nocc, o.degree, tol_eig, o.maxpass,
+        r = api.ks_eigensolve(self.mesh, self.v, self.X, self.nconv, o.degree, tol_eig, o.maxpass,
                               prec=o.filter_prec, switch_tol=o.switch_tol, work=self.work_eig)
+        # at finite temperature the eigensolver's gap test at nconv has no meaning
+        ok = (L.FE_OK, L.FE_EGAP) if o.kT > 0 else (L.FE_OK,)
+        if r.status not in ok:
+            raise L.FEError(r.status, "ks_eigensolve")
+        self.eig = r.eig
+        if o.kT > 0:
+            oc = api.fermi_occupations(r.eig[:self.nconv], self.n_elec, o.kT, o.smax, o.occ_cut)
+            self.state = OccState(oc.n_incl, oc.occ[:oc.n_incl], r.eig[:oc.n_incl], oc.mu)
+        else:
+            self.state = OccState(self.nconv, [2.0] * self.nconv, r.eig[:self.nconv])
         torch.cuda.current_stream().synchronize()
         self.stats.t_forward += time.perf_counter() - t0
         self.stats.passes.append(r.passes)
         self.stats.n_forward += 1
-        if r.status not in (L.FE_OK,):
-            raise L.FEError(r.status, "ks_eigensolve")
-        self.eig = r.eig
         return r
 
     def psi(self):
-        return self.X[:, :self.nocc].contiguous()
+        return self.X[:, :self.state.n].contiguous()
 
     def loss_and_rhs(self, Psi):
-        rho, B, loss = api.loss_grad(self.mesh, Psi, self.occ, self.rho_data, work=self.work_lg)
+        rho, B, loss = api.loss_grad(self.mesh, Psi, self.state.occ, self.rho_data, work=self.work_lg)
         self.last_loss = loss
         return rho, B, loss
 
-    def gradient(self, Psi, B):
+    def gradient(self, Psi, B, rho=None, state: OccState | None = None):
+        """dL/du from the orbitals, the adjoint right-hand sides and (finite T) the density."""
         o = self.opts
+        st = state or self.state
         _, tol_adj = self.tolerances()
         t0 = time.perf_counter()
-        Q, ar = api.adjoint_solve(self.mesh, self.v, Psi, self.eig[:self.nocc], B, tol=tol_adj,
+        Q, ar = api.adjoint_solve(self.mesh, self.v, Psi, st.eig, B, tol=tol_adj,
                                   maxit=o.maxit_adj, prec=o.adjoint_prec, work=self.work_adj)
-        g = api.loss_grad(self.mesh, Psi, self.occ, self.rho_data, Q=Q, tau_bc=o.tau_bc, work=self.work_lg)
+        if o.kT > 0:
+            api.adjoint_along_psi(self.mesh, Psi, st.eig, st.mu, o.kT, rho, self.rho_data, Q, smax=o.smax,
+                                  work=self.work_ap)
+        g = api.loss_grad(self.mesh, Psi, st.occ, self.rho_data, Q=Q, tau_bc=o.tau_bc, work=self.work_lg)
         torch.cuda.current_stream().synchronize()
         self.stats.t_adjoint += time.perf_counter() - t0
         self.stats.adj_iters.append(max(ar.iters))
@@ -130,7 +168,7 @@ class InverseProblem:
         rho, B, loss = self.loss_and_rhs(Psi)
         if not want_grad:
             return loss, None
-        return loss, self.gradient(Psi, B)
+        return loss, self.gradient(Psi, B, rho)
 
 
 class InvDFTLoss(torch.autograd.Function):
@@ -144,10 +182,11 @@ class InvDFTLoss(torch.autograd.Function):
         Psi = prob.psi()
         rho, B, loss = prob.loss_and_rhs(Psi)
         ctx.prob = prob
+        ctx.state = prob.state
         if prob.opts.recompute:
             ctx.save_for_backward(u)               # orbitals are recomputed in backward
         else:
-            ctx.save_for_backward(u, Psi, B)
+            ctx.save_for_backward(u, Psi, B, rho)
         return torch.tensor(loss, dtype=torch.float64, device=u.device)
 
     @staticmethod
@@ -159,10 +198,12 @@ class InvDFTLoss(torch.autograd.Function):
             tol_eig, _ = prob.tolerances()
             prob.eigensolve(tol_eig)             # warm block is already converged: ~1 pass
             Psi = prob.psi()
-            _, B, _ = prob.loss_and_rhs(Psi)
+            rho, B, _ = prob.loss_and_rhs(Psi)
+            state = prob.state
         else:
-            u, Psi, B = ctx.saved_tensors
-        g = prob.gradient(Psi, B)
+            u, Psi, B, rho = ctx.saved_tensors
+            state = ctx.state
+        g = prob.gradient(Psi, B, rho, state)
         api.axpby(0.0, g, float(gL), g)            # g <- gL * g
         return g, None
 

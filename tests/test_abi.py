@@ -74,6 +74,20 @@ def test_argument_checks_without_gpu():
     assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
     assert lib.fe_apply_timing(0) == _lib.FE_OK
     assert lib.fe_apply_timing_read(_lib.FE_BF16, None, None, None) == _lib.FE_EINVAL
+    # finite temperature: argument checks return before any arithmetic
+    eig = (C.c_double * 3)(-1.0, 0.0, 1.0)
+    bad = (C.c_double * 3)(0.0, -1.0, 1.0)
+    occ = (C.c_double * 3)()
+    assert lib.fermi_occupations(eig, 3, 2.0, 0.0, 2.0, 1e-12, occ, None, None, None) == _lib.FE_EINVAL
+    assert lib.fermi_occupations(eig, 3, 6.0, 0.1, 2.0, 1e-12, occ, None, None, None) == _lib.FE_EINVAL
+    assert lib.fermi_occupations(eig, 3, 0.0, 0.1, 2.0, 1e-12, occ, None, None, None) == _lib.FE_EINVAL
+    assert lib.fermi_occupations(bad, 3, 2.0, 0.1, 2.0, 1e-12, occ, None, None, None) == _lib.FE_EINVAL
+    assert b"ascend" in lib.fe_last_error()
+    assert lib.fermi_occupations(eig, 3, 2.0, 0.1, 2.0, 1.0, occ, None, None, None) == _lib.FE_EINVAL
+    assert lib.fermi_occupations(None, 3, 2.0, 0.1, 2.0, 1e-12, occ, None, None, None) == _lib.FE_EINVAL
+    assert lib.adjoint_along_psi(null, None, 1, None, 0.0, 0.1, 2.0, None, None, None, None, None, None,
+                                 None) == _lib.FE_EINVAL
+    assert lib.fe_workspace_bytes(null, _lib.FE_OP_ALONG_PSI, 4, 0) == 0
 
 
 def test_status_exceptions_carry_message():
