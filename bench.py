@@ -19,7 +19,13 @@ doubles (launched at start-up as the reference), stored under profiles/ with
 the hash of the kernel source they were taken on; it is null when the kernel
 source has changed since.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5]
+With --kT T (Ha) the same loop runs at finite temperature: Fermi-Dirac
+occupations with mu from the electron count, every orbital above the occupation
+cut in the density and the adjoint, and the in-span part of the adjoint functions
+(Eqs. 4, 5, 8, 9). The block is widened by 4 columns and the eigensolver converges
+all but the last 4 Ritz pairs; the included count is reported in `config`.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0]
 """
 from __future__ import annotations
 
@@ -131,6 +137,7 @@ def main():
     ap.add_argument("--apply-only", action="store_true",
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--kT", type=float, default=0.0, help="k_B T in Ha (0: zero temperature)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -156,7 +163,13 @@ def main():
     v_star = torch.tensor(wl.v_xc_target(xyz_h), device=dev)
     del xyz_h
     nocc, nv = wl.n_occ, wl.n_occ + wl.n_buf
-    log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}")
+    kT = args.kT
+    nconv = nocc
+    if kT > 0:
+        nv += 4
+        nconv = nv - 4
+    wname = wl.name if kT <= 0 else f"{wl.name}-kT{kT:g}"
+    log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}" + (f" kT={kT} converged={nconv}" if kT > 0 else ""))
     # a plain streaming kernel of known size, the reference for scaling the HBM byte
     # counters of profiled runs: fe_axpby over 2^27 doubles reads 2 GiB and writes 1 GiB
     xa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -178,21 +191,37 @@ def main():
 
     # target density rho_data = rho(v_fixed + v*) (untimed set-up)
     t0 = time.perf_counter()
-    v_t = v_fixed + v_star
-    Xt = X0.clone()
-    r = api.ks_eigensolve(mesh, v_t, Xt, nocc, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
-    rho_d, _, _ = api.loss_grad(mesh, Xt[:, :nocc].contiguous(), [2.0] * nocc, torch.zeros_like(v_t), want_B=False)
-    del Xt, v_t
+    if kT > 0:
+        # at the same temperature, through the driver (occupations from fermi_occupations)
+        tp = inv.InverseProblem(mesh, v_fixed, torch.zeros_like(v_fixed), wl.n_elec, X0,
+                                inv.SolverOptions(degree=wl.cheb_degree, tol_eig=1e-9, maxpass=400, kT=kT,
+                                                  n_states=nconv, filter_prec="f32", switch_tol=1e-4))
+        tp.set_potential(v_star)
+        tp.eigensolve(1e-9)
+        rho_d, _, _ = tp.loss_and_rhs(tp.psi())
+        target_passes, target_incl = tp.stats.passes[-1], tp.state.n
+        del tp
+    else:
+        v_t = v_fixed + v_star
+        Xt = X0.clone()
+        r = api.ks_eigensolve(mesh, v_t, Xt, nocc, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+        rho_d, _, _ = api.loss_grad(mesh, Xt[:, :nocc].contiguous(), [2.0] * nocc, torch.zeros_like(v_t),
+                                    want_B=False)
+        target_passes = r.passes
+        del Xt, v_t
     # warm start for the inverse loop: orbitals of v_fixed (u = 0)
     Xw = X0.clone()
-    api.ks_eigensolve(mesh, v_fixed, Xw, nocc, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+    api.ks_eigensolve(mesh, v_fixed, Xw, nconv, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
     torch.cuda.synchronize()
-    log(f"set-up (target density + initial orbitals) {time.perf_counter() - t0:.1f} s, target passes {r.passes}")
+    log(f"set-up (target density + initial orbitals) {time.perf_counter() - t0:.1f} s, "
+        f"target passes {target_passes}" + (f", {target_incl} orbitals enter" if kT > 0 else ""))
     del X0
 
     step_len = 0.01
     results = {}
     common = dict(degree=wl.cheb_degree, tol_eig=1e-9, tol_adj=1e-10, maxpass=100, maxit_adj=20000)
+    if kT > 0:
+        common.update(kT=kT, n_states=nconv)
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
         "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=1e-4,
@@ -202,7 +231,8 @@ def main():
         log(f"path {name}")
         el, losses, g0, prob, timing = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name],
                                                 args.steps, args.warmup, step_len)
-        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats, timing=timing)
+        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats, timing=timing,
+                             n_incl=prob.state.n)
         for p_, (n_, ms_, b_) in timing.items():
             if n_:
                 log(f"  ks_apply {p_}: {n_} launches, {ms_:.1f} ms, {b_ / ms_ / 1e6:.0f} GB/s")
@@ -232,7 +262,7 @@ def main():
     dom = max(tim, key=lambda p: tim[p][1])
     n_l, ms_l, b_l = tim[dom]
     achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
-    traffic = read_traffic(dom, wl.name)
+    traffic = read_traffic(dom, wname)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
@@ -242,10 +272,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import fe as ofe
-        log("cpu baseline: one oracle Kronecker apply of the occupied block on the full mesh")
+        log("cpu baseline: one oracle Kronecker apply of the orbital block on the full mesh")
         om = ofe.mesh3d(wl.p, wl.n, wl.half_width)
         rng = np.random.default_rng(5)
-        Xc = rng.standard_normal((om.n_free, nocc))
+        ncol = head["n_incl"]                      # the orbital block the head path carries
+        Xc = rng.standard_normal((om.n_free, ncol))
         vc = v_fixed.cpu().numpy()
         t0 = time.perf_counter()
         ofe.hamiltonian_apply(om, vc, Xc)
@@ -256,7 +287,7 @@ def main():
         applies = passes * (wl.cheb_degree + 1) + sum(st.adj_iters) / max(1, len(st.adj_iters)) + 2
         cpu = {"value": 1.0 / (t_apply * applies), "unit": "grad_iter/s", "cores": os.cpu_count(),
                "kind": "oracle",
-               "sample": (f"one FP64 oracle Kronecker apply of the {nocc}-column block on the {om.n_free}-node "
+               "sample": (f"one FP64 oracle Kronecker apply of the {ncol}-column block on the {om.n_free}-node "
                           f"mesh ({t_apply:.1f} s), scaled by {applies:.0f} applies per gradient iteration "
                           f"(the GPU path's measured filter passes x degree + MINRES iterations)")}
 
@@ -273,8 +304,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if "mixed" in results else "f64",
         "data": "synthetic (seeded model molecule; target density from a known potential)",
-        "config": {"workload": wl.name, "p": wl.p, "cells_per_dim": wl.n, "half_width": wl.half_width,
-                   "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree},
+        "config": {"workload": wname, "p": wl.p, "cells_per_dim": wl.n, "half_width": wl.half_width,
+                   "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree,
+                   **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {})},
         "ks_apply_GBps_f32": gbs32,
         "ks_apply_GBps_f64": gbs64,
         "ks_apply_ms_f32": ms32,
