@@ -15,6 +15,8 @@ finite-element inverse DFT (Sec. 2 and Sec. 3.2):
                 (Eqs. 11, 22), central finite differences, L-BFGS (Eq. 21).
 * ``chfsi``   — the Chebyshev filter polynomial and Rayleigh-Ritz projection
                 (Sec. 3.2.2, Eqs. 23-24) by their plain definitions.
+* ``vxcmesh`` — the XC potential on its own linear mesh (Eq. 14): the prolongation
+                to the orbital nodes and the gradient's transpose (Eq. 22).
 * ``thermal`` — finite temperature: Fermi-Dirac occupancy and mu (Eqs. 4, 5), the
                 adjoint of each degenerate block with Eqs. 8-9 (Sec. 2, Sec. 3.2.2),
                 the gradient of Eq. 10.

@@ -154,3 +154,25 @@ def random_directions(n_rows: int, k: int, seed: int) -> np.ndarray:
     d = rng.standard_normal((k, n_rows))
     d /= np.max(np.abs(d), axis=1, keepdims=True)
     return d
+
+
+def vxc_vertices(L: float, h_v: float, inner: float, growth: float = 1.5) -> np.ndarray:
+    """1-D vertex list of the linear mesh for the XC potential on [-L, L]: uniform cells of
+    size h_v on [-inner, inner] (the inner cuboid), then cells growing by `growth` towards
+    the boundary (the outer cuboid), the last one ending at +-L (a sliver is merged into
+    its neighbour). Symmetric about 0. Mesh parameters are inputs, shared by both sides."""
+    n_in = max(1, int(round(min(inner, L) / h_v)))
+    if n_in * h_v >= L:
+        n = max(1, int(round(L / h_v)))
+        return np.linspace(-L, L, 2 * n + 1)
+    right = [n_in * h_v]
+    h = h_v
+    while right[-1] < L:
+        h *= growth
+        right.append(right[-1] + h)
+    right[-1] = L
+    if len(right) > 2 and right[-1] - right[-2] < 0.5 * (right[-2] - right[-3]):
+        right.pop(-2)
+    core = np.linspace(-n_in * h_v, n_in * h_v, 2 * n_in + 1)
+    right = np.array(right[1:])
+    return np.concatenate([-right[::-1], core, right])

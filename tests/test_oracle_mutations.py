@@ -129,3 +129,21 @@ def test_thermal_pin_catches_occupancy_without_spin_factor(monkeypatch):
     orig = th.occupancy
     monkeypatch.setattr(th, "occupancy", lambda e, mu, kT, smax=2.0: orig(e, mu, kT, 1.0))
     assert _thermal_fd_mismatch() > 1e-3
+
+
+# ------------------------------------------------------- linear v_xc mesh (Eq. 14)
+def test_vxc_pin_catches_swapped_hat_weights(monkeypatch):
+    from oracle import vxcmesh as vm
+    from synth import vxc_vertices
+
+    def mismatch():
+        m = fe.mesh3d(3, 2, 3.0)
+        t = vxc_vertices(3.0, 0.8, 1.5, 1.5)
+        P = vm.prolongation(m, t, t, t)
+        V = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        return np.abs(P @ (1.0 + V[:, 0] - 2 * V[:, 2]) - (1.0 + m.coords()[:, 0] - 2 * m.coords()[:, 2])).max()
+
+    assert mismatch() < 1e-12
+    orig = vm.hat_weights
+    monkeypatch.setattr(vm, "hat_weights", lambda t, x: [(c, 1.0 - w) for c, w in orig(t, x)])
+    assert mismatch() > 1e-2
