@@ -25,7 +25,12 @@ cut in the density and the adjoint, and the in-span part of the adjoint function
 (Eqs. 4, 5, 8, 9). The block is widened by 4 columns and the eigensolver converges
 all but the last 4 Ritz pairs; the included count is reported in `config`.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0]
+With --vxc-h H the XC potential lives on its own linear mesh (Eq. 14): uniform cells of
+H bohr on the inner cube [-L/2, L/2]^3, growing by 1.4 towards the box; the loop
+optimises its vertex values (v = v_fixed + P u, gradient P^T g), and the two transfer
+kernels are timed on their own as well.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0] [--vxc-h 0]
 """
 from __future__ import annotations
 
@@ -91,10 +96,10 @@ def read_traffic(prec, workload_name):
     return None
 
 
-def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, step_len):
+def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, step_len, vxc=None):
     import torch
-    prob = inv.InverseProblem(mesh, v_fixed, rho_d, n_elec, X0, opts)
-    u = torch.zeros_like(v_fixed)
+    prob = inv.InverseProblem(mesh, v_fixed, rho_d, n_elec, X0, opts, vxc=vxc)
+    u = prob.zeros_u()
     losses, grads = [], []
 
     def one_step(u):
@@ -138,6 +143,8 @@ def main():
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kT", type=float, default=0.0, help="k_B T in Ha (0: zero temperature)")
+    ap.add_argument("--vxc-h", type=float, default=0.0,
+                    help="cell size of the linear XC mesh on the inner cube (0: nodal XC potential)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -149,7 +156,7 @@ def main():
 
     from paper_2510_10529_amd import api
     from paper_2510_10529_amd import inverse as inv
-    from synth import random_block, workload
+    from synth import random_block, vxc_vertices, workload
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -169,6 +176,8 @@ def main():
         nv += 4
         nconv = nv - 4
     wname = wl.name if kT <= 0 else f"{wl.name}-kT{kT:g}"
+    if args.vxc_h > 0:
+        wname += f"-vxc{args.vxc_h:g}"
     log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}" + (f" kT={kT} converged={nconv}" if kT > 0 else ""))
     # a plain streaming kernel of known size, the reference for scaling the HBM byte
     # counters of profiled runs: fe_axpby over 2^27 doubles reads 2 GiB and writes 1 GiB
@@ -217,6 +226,38 @@ def main():
         f"target passes {target_passes}" + (f", {target_incl} orbitals enter" if kT > 0 else ""))
     del X0
 
+    vxc = None
+    vxc_info = {}
+    if args.vxc_h > 0:
+        tv = vxc_vertices(wl.half_width, args.vxc_h, 0.5 * wl.half_width, 1.4)
+        vxc = api.VxcMesh(mesh, tv, tv, tv)
+        log(f"linear XC mesh: {tv.size} vertices per axis, {vxc.n_vertices} unknowns")
+        # the two transfer kernels alone (HIP events on the current stream)
+        ut = torch.randn(vxc.n_vertices, dtype=torch.float64, device=dev)
+        vt_ = torch.empty_like(v_fixed)
+        ft = torch.empty_like(ut)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for _ in range(3):
+            vxc.prolong(ut, base=v_fixed, out=vt_)
+            vxc.restrict(vt_, out=ft)
+        reps = 20
+        ev[0].record()
+        for _ in range(reps):
+            vxc.prolong(ut, base=v_fixed, out=vt_)
+        ev[1].record()
+        for _ in range(reps):
+            vxc.restrict(vt_, out=ft)
+        ev[2].record()
+        ev[2].synchronize()
+        ms_p, ms_r = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+        nb_p = 16 * mesh.n_free + 8 * vxc.n_vertices      # base read, v written, u read once
+        nb_r = 8 * mesh.n_free + 8 * vxc.n_vertices       # g read once, f written
+        vxc_info = {"vxc_vertices": vxc.n_vertices, "vxc_prolong_ms": ms_p, "vxc_prolong_GBps": nb_p / ms_p / 1e6,
+                    "vxc_restrict_ms": ms_r, "vxc_restrict_GBps": nb_r / ms_r / 1e6}
+        log(f"vxc prolong {ms_p:.3f} ms ({nb_p / ms_p / 1e6:.0f} GB/s), restrict {ms_r:.3f} ms "
+            f"({nb_r / ms_r / 1e6:.0f} GB/s)")
+        del ut, vt_, ft
+
     step_len = 0.01
     results = {}
     common = dict(degree=wl.cheb_degree, tol_eig=1e-9, tol_adj=1e-10, maxpass=100, maxit_adj=20000)
@@ -230,7 +271,7 @@ def main():
     for name in args.paths.split(","):
         log(f"path {name}")
         el, losses, g0, prob, timing = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name],
-                                                args.steps, args.warmup, step_len)
+                                                args.steps, args.warmup, step_len, vxc)
         results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats, timing=timing,
                              n_incl=prob.state.n)
         for p_, (n_, ms_, b_) in timing.items():
@@ -306,12 +347,14 @@ def main():
         "data": "synthetic (seeded model molecule; target density from a known potential)",
         "config": {"workload": wname, "p": wl.p, "cells_per_dim": wl.n, "half_width": wl.half_width,
                    "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree,
-                   **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {})},
+                   **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {}),
+                   **({"vxc_h": args.vxc_h, "vxc_vertices": vxc.n_vertices} if vxc is not None else {})},
         "ks_apply_GBps_f32": gbs32,
         "ks_apply_GBps_f64": gbs64,
         "ks_apply_ms_f32": ms32,
         "ks_apply_ms_f64": ms64,
         **out_extra,
+        **vxc_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -56,6 +56,7 @@ extern "C" {
 #endif
 
 typedef struct fe_mesh_s* fe_mesh;
+typedef struct vxc_mesh_s* vxc_mesh;
 
 typedef enum {
   FE_OK = 0,
@@ -196,6 +197,35 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
 fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc,
                     const double* rho_data, const double* Q, double tau_bc, double* rho, double* B,
                     double* grad, double* loss_h, void* work, void* stream);
+
+/* --------------------------------------------------------- vxc_mesh ------
+ * The exchange-correlation potential on its own linear finite-element mesh
+ * (Eq. 14: first-order elements, uniform in an inner cuboid and coarsening
+ * outwards, Sec. 4) and the transfer to the orbital mesh. The linear mesh is the
+ * tensor product of three 1-D vertex lists t^x (mx + 1 strictly increasing
+ * host doubles), t^y, t^z with trilinear hat functions N_b; the unknowns are the
+ * (mx+1)(my+1)(mz+1) vertex values, b = ix + (mx+1)(iy + (my+1) iz). The lists
+ * must cover every free node of the orbital mesh.
+ * With the orbital mesh's GLL quadrature the potential enters H~ through its
+ * nodal values v_a = sum_b N_b(x_a) u_b = (P u)_a, and the gradient with respect
+ * to u is f = P^T g for the nodal gradient g of loss_grad (Eq. 22).
+ * vxc_mesh_create copies the tables to the current device and allocates the
+ * restriction's two intermediate arrays, n1^2 (mx+1) and n1 (my+1)(mx+1) doubles
+ * with n1 the free nodes per axis (the mesh handle is not retained). Errors: FE_EINVAL (NULL pointers, fewer than one cell on an
+ * axis, vertices not increasing, nodes not covered), FE_ENOMEM, FE_EDEVICE. */
+fe_status vxc_mesh_create(fe_mesh mesh, int mx, const double* tx_h, int my, const double* ty_h, int mz,
+                          const double* tz_h, vxc_mesh* out);
+/* Number of linear-mesh unknowns and vertices per axis (3 ints); either may be NULL. */
+fe_status vxc_mesh_info(vxc_mesh vm, int64_t* n_vertices_h, int* vertices_per_axis_h);
+fe_status vxc_mesh_destroy(vxc_mesh vm);
+/* v = base + P u over the N_f free nodes (base may be NULL: v = P u). u: the
+ * vertex values; u must not alias v or base (base may alias v). Asynchronous. */
+fe_status vxc_prolong(vxc_mesh vm, const double* u, const double* base, double* v, void* stream);
+/* f = P^T g: g over the N_f free nodes, f over the vertices (f must not alias g).
+ * Three 1-D passes, each summing a support in a fixed order (bitwise
+ * reproducible). The passes use two intermediate arrays owned by the handle, so
+ * calls on one handle must not overlap (one stream at a time). Asynchronous. */
+fe_status vxc_restrict(vxc_mesh vm, const double* g, double* f, void* stream);
 
 /* ----------------------------------------------------- fermi_occupations --
  * Finite-temperature occupations (Eq. 4's Fermi-Dirac occupancy, Eq. 5):

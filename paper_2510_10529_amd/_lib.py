@@ -44,6 +44,11 @@ SIGNATURES = {
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),
     "fe_apply_timing": (C.c_int, [C.c_int]),
     "fe_apply_timing_read": (C.c_int, [C.c_int, i64p, dp, dp]),
+    "vxc_mesh_create": (C.c_int, [vp, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.POINTER(vp)]),
+    "vxc_mesh_info": (C.c_int, [vp, i64p, ip]),
+    "vxc_mesh_destroy": (C.c_int, [vp]),
+    "vxc_prolong": (C.c_int, [vp, vp, vp, vp, vp]),
+    "vxc_restrict": (C.c_int, [vp, vp, vp, vp]),
     "fermi_occupations": (C.c_int, [dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp,
                                     ip]),
     "adjoint_along_psi": (C.c_int, [vp, vp, C.c_int, dp, C.c_double, C.c_double, C.c_double, vp, vp, vp, dp,

@@ -85,6 +85,56 @@ class Mesh:
         return int(L.load().fe_workspace_bytes(self._h, op, nv, PREC[prec]))
 
 
+class VxcMesh:
+    """Linear tensor mesh of the XC potential (Eq. 14) and its transfer to a Mesh's nodes."""
+
+    def __init__(self, mesh: Mesh, tx, ty=None, tz=None):
+        ty = tx if ty is None else ty
+        tz = tx if tz is None else tz
+        self.vertices = [list(map(float, t)) for t in (tx, ty, tz)]
+        h = C.c_void_p()
+        ms = [len(t) - 1 for t in self.vertices]
+        L.check(L.load().vxc_mesh_create(mesh.handle, ms[0], _host_doubles(self.vertices[0]), ms[1],
+                                         _host_doubles(self.vertices[1]), ms[2], _host_doubles(self.vertices[2]),
+                                         C.byref(h)), "vxc_mesh_create")
+        self._h = h
+        self.mesh = mesh
+        nv = C.c_int64()
+        per = (C.c_int * 3)()
+        L.check(L.load().vxc_mesh_info(h, C.byref(nv), per), "vxc_mesh_info")
+        self.n_vertices = nv.value
+        self.shape = tuple(per)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            L.load().vxc_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prolong(self, u, base=None, out=None):
+        """v = base + P u on the orbital nodes."""
+        if out is None:
+            out = torch.empty(self.mesh.n_free, dtype=torch.float64, device=u.device)
+        L.check(L.load().vxc_prolong(self._h, _ptr(u), _ptr(base), _ptr(out), _stream()), "vxc_prolong")
+        return out
+
+    def restrict(self, g, out=None):
+        """f = P^T g on the vertices."""
+        if out is None:
+            out = torch.empty(self.n_vertices, dtype=torch.float64, device=g.device)
+        L.check(L.load().vxc_restrict(self._h, _ptr(g), _ptr(out), _stream()), "vxc_restrict")
+        return out
+
+
 def ks_apply(mesh: Mesh, v, X, Y=None, shift=None, prec: str = "f64"):
     """Y = H~ X - X diag(shift) (one call of the C ABI)."""
     nv = X.shape[1]

@@ -23,6 +23,8 @@ struct fe_mesh_s {
 
 namespace invdft {
 
+const Mesh* mesh_tables(fe_mesh mesh) { return mesh ? &mesh->m : nullptr; }
+
 static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }

@@ -34,6 +34,9 @@ struct Mesh {
   double* d_md1 = nullptr;
 };
 
+// the tables behind a mesh handle (NULL for a NULL handle)
+const Mesh* mesh_tables(fe_mesh mesh);
+
 // thread-local error text
 void set_error(const std::string& msg);
 fe_status fail(fe_status st, const std::string& msg);

@@ -7,6 +7,10 @@ Backward: optionally recompute the orbitals (from the warm-start block, so they
 need not be kept between forward and backward), solve the adjoint equations by
 batched projected MINRES (Eq. 20) and form g_b = sum_i psi_{b,i} q_{b,i} (Eq. 22).
 
+XC potential on its own linear mesh (a VxcMesh, Eq. 14): u holds its vertex values,
+v = v_fixed + P u, and the gradient is P^T g (Eq. 22's integral against the linear
+hat functions, by the orbital mesh's quadrature).
+
 Finite temperature (kT > 0): the occupations are Fermi-Dirac with mu from the
 electron count (Eqs. 4, 5); every orbital with f_i above a cut enters the density
 and the adjoint, and the adjoint functions gain their component along the included
@@ -71,8 +75,9 @@ class InverseProblem:
     """One inverse-DFT problem on one GPU: mesh, fixed potential, target density."""
 
     def __init__(self, mesh: api.Mesh, v_fixed: torch.Tensor, rho_data: torch.Tensor, n_elec: int,
-                 X0: torch.Tensor, opts: SolverOptions | None = None):
+                 X0: torch.Tensor, opts: SolverOptions | None = None, vxc: api.VxcMesh | None = None):
         self.mesh = mesh
+        self.vxc = vxc                         # None: u is nodal on the orbital mesh
         self.v_fixed = v_fixed
         self.rho_data = rho_data
         self.n_elec = n_elec
@@ -100,8 +105,16 @@ class InverseProblem:
 
     # ------------------------------------------------------------------ pieces
     def set_potential(self, u: torch.Tensor):
+        if self.vxc is not None:
+            self.vxc.prolong(u, base=self.v_fixed, out=self.v)     # v = v_fixed + P u
+            return
         self.v.copy_(self.v_fixed)                  # device copy
         api.axpby(1.0, u, 1.0, self.v)              # v = v_fixed + u
+
+    def zeros_u(self):
+        """A zero potential update in the unknowns u lives in."""
+        n = self.vxc.n_vertices if self.vxc is not None else self.mesh.n_free
+        return torch.zeros(n, dtype=torch.float64, device=self.v_fixed.device)
 
     def tolerances(self):
         o = self.opts
@@ -151,6 +164,8 @@ class InverseProblem:
             api.adjoint_along_psi(self.mesh, Psi, st.eig, st.mu, o.kT, rho, self.rho_data, Q, smax=o.smax,
                                   work=self.work_ap)
         g = api.loss_grad(self.mesh, Psi, st.occ, self.rho_data, Q=Q, tau_bc=o.tau_bc, work=self.work_lg)
+        if self.vxc is not None:
+            g = self.vxc.restrict(g)                                 # f = P^T g
         torch.cuda.current_stream().synchronize()
         self.stats.t_adjoint += time.perf_counter() - t0
         self.stats.adj_iters.append(max(ar.iters))

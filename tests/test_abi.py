@@ -88,6 +88,14 @@ def test_argument_checks_without_gpu():
     assert lib.adjoint_along_psi(null, None, 1, None, 0.0, 0.1, 2.0, None, None, None, None, None, None,
                                  None) == _lib.FE_EINVAL
     assert lib.fe_workspace_bytes(null, _lib.FE_OP_ALONG_PSI, 4, 0) == 0
+    # linear XC mesh
+    t = (C.c_double * 3)(-1.0, 0.0, 1.0)
+    vmh = C.c_void_p()
+    assert lib.vxc_mesh_create(null, 2, t, 2, t, 2, t, C.byref(vmh)) == _lib.FE_EINVAL
+    assert lib.vxc_mesh_info(null, None, None) == _lib.FE_EINVAL
+    assert lib.vxc_prolong(null, None, None, None, None) == _lib.FE_EINVAL
+    assert lib.vxc_restrict(null, None, None, None) == _lib.FE_EINVAL
+    assert lib.vxc_mesh_destroy(null) == _lib.FE_OK
 
 
 def test_status_exceptions_carry_message():
