@@ -107,10 +107,21 @@ class Mesh1D:
     x_all: np.ndarray    # all node coordinates (0..pn)
 
 
-def mesh1d(p: int, n: int, L: float) -> Mesh1D:
-    """Assemble the 1-D operators: K1 = sum_e (2/h) K^, Mc = sum_e (h/2) M^,
-    W1 = sum_e (h/2) w^ over the n elements, then drop the two Dirichlet ends."""
-    h = 2.0 * L / n
+def mesh1d(p: int, n: int, L: float, breaks: np.ndarray | None = None) -> Mesh1D:
+    """Assemble the 1-D operators: K1 = sum_e (2/h_e) K^, Mc = sum_e (h_e/2) M^,
+    W1 = sum_e (h_e/2) w^ over the n elements, then drop the two Dirichlet ends.
+
+    Uniform cells of h = 2L/n on [-L, L], or, with ``breaks`` (n + 1 increasing cell
+    boundaries), the graded mesh they define (cell e of width h_e = breaks[e+1] - breaks[e]);
+    ``h`` is then the smallest width and L half the extent.
+    """
+    if breaks is None:
+        t = -L + (2.0 * L / n) * np.arange(n + 1)
+    else:
+        t = np.asarray(breaks, dtype=np.float64)
+        n = t.size - 1
+        L = 0.5 * (t[-1] - t[0])
+    hs = np.diff(t)
     Kh, Mh, xi, wg = reference_matrices(p)
     N = p * n + 1
     K = np.zeros((N, N))
@@ -118,13 +129,14 @@ def mesh1d(p: int, n: int, L: float) -> Mesh1D:
     W = np.zeros(N)
     x = np.zeros(N)
     for e in range(n):
+        h = hs[e]
         idx = e * p + np.arange(p + 1)
         K[np.ix_(idx, idx)] += (2.0 / h) * Kh
         M[np.ix_(idx, idx)] += (h / 2.0) * Mh
         W[idx] += (h / 2.0) * wg
-        x[idx] = -L + h * (e + (xi + 1.0) / 2.0)
+        x[idx] = -L + h * (e + (xi + 1.0) / 2.0) if breaks is None else t[e] + h * (xi + 1.0) / 2.0
     f = slice(1, N - 1)
-    return Mesh1D(p=p, n=n, L=L, h=h, x=x[f].copy(), K1=K[f, f].copy(), Mc=M[f, f].copy(),
+    return Mesh1D(p=p, n=n, L=L, h=float(hs.min()), x=x[f].copy(), K1=K[f, f].copy(), Mc=M[f, f].copy(),
                   W1=W[f].copy(), x_all=x)
 
 
@@ -155,6 +167,12 @@ class Mesh3D:
 
 def mesh3d(p: int, n: int, L: float) -> Mesh3D:
     return Mesh3D(mesh1d(p, n, L))
+
+
+def mesh3d_graded(p: int, breaks: np.ndarray) -> Mesh3D:
+    """The tensor product of one graded 1-D mesh on every axis (cells of different widths;
+    the Kronecker form of K holds because every cell is a product of 1-D cells)."""
+    return Mesh3D(mesh1d(p, 0, 0.0, breaks=breaks))
 
 
 def kinetic_csr(mesh: Mesh3D) -> sp.csr_matrix:
