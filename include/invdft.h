@@ -92,6 +92,17 @@ typedef enum {
  * Errors: FE_EINVAL (bad p, n, L or out == NULL), FE_ENOMEM, FE_EDEVICE. */
 fe_status fe_mesh_create(int p, int n_cells_per_dim, double half_width, fe_mesh* out);
 
+/* A graded tensor mesh (cells of different widths, Fig. 6 and the mesh parameters
+ * of Sec. 4): the same n cells on every axis, cell e spanning
+ * [breaks_h[e], breaks_h[e+1]] (n + 1 strictly increasing host doubles). Every
+ * cell is a product of 1-D cells, so the operator keeps its Kronecker form with
+ * 1-D factors assembled from per-cell element matrices K_e = (2/h_e) K^,
+ * M_e = (h_e/2) M^, W_e = (h_e/2) w^; the apply carries the per-cell factors.
+ * The kinetic bound uses the smallest cell. Everything else is as fe_mesh_create.
+ * Errors: FE_EINVAL (NULL pointers, p outside [1, 8], n < 1, boundaries not
+ * strictly increasing), FE_ENOMEM, FE_EDEVICE. */
+fe_status fe_mesh_create_graded(int p, int n_cells_per_dim, const double* breaks_h, fe_mesh* out);
+
 /* Sizes and the kinetic spectral bound; any output pointer may be NULL. */
 fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h,
                        int* nodes_per_cell_h, double* kin_bound_h);

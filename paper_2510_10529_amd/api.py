@@ -44,10 +44,19 @@ def _work(nbytes: int, device):
 class Mesh:
     """Spectral-element mesh of [-L, L]^3 with n^3 cells of order p (device tables)."""
 
-    def __init__(self, p: int, n: int, half_width: float):
+    def __init__(self, p: int, n: int, half_width: float, breaks=None):
+        """Uniform cells of 2 half_width / n on [-half_width, half_width]^3, or, with ``breaks``
+        (n + 1 increasing cell boundaries, the same on every axis), the graded mesh they define."""
         lib = L.load()
         h = C.c_void_p()
-        L.check(lib.fe_mesh_create(int(p), int(n), float(half_width), C.byref(h)), "fe_mesh_create")
+        if breaks is None:
+            L.check(lib.fe_mesh_create(int(p), int(n), float(half_width), C.byref(h)), "fe_mesh_create")
+        else:
+            breaks = [float(b) for b in breaks]
+            n = len(breaks) - 1
+            half_width = 0.5 * (breaks[-1] - breaks[0])
+            L.check(lib.fe_mesh_create_graded(int(p), n, _host_doubles(breaks), C.byref(h)), "fe_mesh_create_graded")
+        self.breaks = breaks
         self._h = h
         self.p, self.n, self.half_width = int(p), int(n), float(half_width)
         nf, nc, npc, kb = C.c_int64(), C.c_int64(), C.c_int(), C.c_double()

@@ -420,11 +420,19 @@ extern "C" {
 
 const char* fe_last_error(void) { return g_err.c_str(); }
 
-fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
+// Shared by the uniform and the graded constructor; t (n + 1 cell boundaries) is NULL for
+// the uniform mesh of [-L, L].
+static fe_status mesh_create_impl(int p, int n, double L, const double* t, fe_mesh* out) {
   if (!out) return fail(FE_EINVAL, "fe_mesh_create: out is NULL");
   *out = nullptr;
   if (p < 1 || p > kMaxP) return fail(FE_EINVAL, "fe_mesh_create: p must be in [1, 8]");
   if (n < 1) return fail(FE_EINVAL, "fe_mesh_create: n must be >= 1");
+  if (t) {
+    for (int e = 0; e < n; ++e)
+      if (!(t[e + 1] > t[e]) || !std::isfinite(t[e]) || !std::isfinite(t[e + 1]))
+        return fail(FE_EINVAL, "fe_mesh_create_graded: cell boundaries must increase strictly");
+    L = 0.5 * (t[n] - t[0]);
+  }
   if (!(L > 0.0) || !std::isfinite(L)) return fail(FE_EINVAL, "fe_mesh_create: half_width must be > 0");
   const long long n1 = (long long)p * n - 1;
   if (n1 > 2000) return fail(FE_EINVAL, "fe_mesh_create: mesh too large");
@@ -437,6 +445,12 @@ fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
   m.L = L;
   m.h = 2.0 * L / n;
   m.nf = n1 * n1 * n1;
+  if (t) {
+    m.graded = true;
+    m.cell_h.resize(n);
+    for (int e = 0; e < n; ++e) m.cell_h[e] = t[e + 1] - t[e];
+    m.h = *std::min_element(m.cell_h.begin(), m.cell_h.end());   // reference width: the smallest
+  }
   const int P1 = p + 1;
   std::vector<double> Kh(P1 * P1), Mh(P1 * P1), xi(P1), wi(P1);
   reference_matrices(p, Kh.data(), Mh.data(), xi.data(), wi.data());
@@ -493,10 +507,26 @@ fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
     const long long g = f + 1;
     const long long e = g / p;
     const int j = (int)(g % p);
-    m.x1[f] = -L + m.h * (e + 0.5 * (xi[j] + 1.0));
-    m.w1[f] = wloc[j];
-    m.kd1[f] = (j == 0) ? m.kt[p * P1 + p] + m.kt[0] : m.kt[j * P1 + j];
-    m.md1[f] = (j == 0) ? m.mt[p * P1 + p] + m.mt[0] : m.mt[j * P1 + j];
+    if (!m.graded) {
+      m.x1[f] = -L + m.h * (e + 0.5 * (xi[j] + 1.0));
+      m.w1[f] = wloc[j];
+      m.kd1[f] = (j == 0) ? m.kt[p * P1 + p] + m.kt[0] : m.kt[j * P1 + j];
+      m.md1[f] = (j == 0) ? m.mt[p * P1 + p] + m.mt[0] : m.mt[j * P1 + j];
+      continue;
+    }
+    // graded: cell e of width he (j > 0), or the vertex between cells e - 1 and e (j = 0)
+    const double he = m.cell_h[e];
+    m.x1[f] = t[e] + 0.5 * he * (xi[j] + 1.0);
+    if (j == 0) {
+      const double hl = m.cell_h[e - 1];
+      m.w1[f] = 0.5 * (hl + he) * wi[0];
+      m.kd1[f] = ((2.0 / hl) * Kh[p * P1 + p] + (2.0 / he) * Kh[0]) / m.w1[f];
+      m.md1[f] = ((0.5 * hl) * Mh[p * P1 + p] + (0.5 * he) * Mh[0]) / m.w1[f];
+    } else {
+      m.w1[f] = 0.5 * he * wi[j];
+      m.kd1[f] = (2.0 / he) * Kh[j * P1 + j] / m.w1[f];
+      m.md1[f] = (0.5 * he) * Mh[j * P1 + j] / m.w1[f];
+    }
   }
   // Fried element bound: (1/2) lambda_max(W_e^{-1/2} K_e W_e^{-1/2}), W_e the element's own lumped mass
   {
@@ -541,6 +571,23 @@ fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
   if (e == hipSuccess) e = hipMemcpy(m.d_w1, m.w1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m.d_kd1, m.kd1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m.d_md1, m.md1.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+  if (m.graded) {
+    // per cell: (h/h_e)^2 and the end-node W1^{-1/2} factors relative to the uniform tables,
+    // whose end nodes carry the weight of two cells of width h_e: sqrt(2 h_e / (h_e + h_nb))
+    std::vector<double> kap(n), gl(n), gr(n);
+    for (int c = 0; c < n; ++c) {
+      const double hc = m.cell_h[c];
+      kap[c] = (m.h / hc) * (m.h / hc);
+      gl[c] = c > 0 ? std::sqrt(2.0 * hc / (hc + m.cell_h[c - 1])) : 1.0;
+      gr[c] = c + 1 < n ? std::sqrt(2.0 * hc / (hc + m.cell_h[c + 1])) : 1.0;
+    }
+    if (e == hipSuccess) e = hipMalloc(&m.d_ckap, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&m.d_cgl, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&m.d_cgr, n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(m.d_ckap, kap.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m.d_cgl, gl.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m.d_cgr, gr.data(), n * sizeof(double), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     fe_mesh_destroy(h);
     return e == hipErrorOutOfMemory ? fail(FE_ENOMEM, "fe_mesh_create: device allocation failed")
@@ -548,6 +595,13 @@ fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) {
   }
   *out = h;
   return FE_OK;
+}
+
+fe_status fe_mesh_create(int p, int n, double L, fe_mesh* out) { return mesh_create_impl(p, n, L, nullptr, out); }
+
+fe_status fe_mesh_create_graded(int p, int n, const double* breaks_h, fe_mesh* out) {
+  if (!breaks_h) return fail(FE_EINVAL, "fe_mesh_create_graded: breaks_h is NULL");
+  return mesh_create_impl(p, n, 0.0, breaks_h, out);
 }
 
 fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h, int* nodes_per_cell_h,
@@ -580,6 +634,9 @@ fe_status fe_mesh_destroy(fe_mesh mesh) {
   if (m.d_w1) (void)hipFree(m.d_w1);
   if (m.d_kd1) (void)hipFree(m.d_kd1);
   if (m.d_md1) (void)hipFree(m.d_md1);
+  if (m.d_ckap) (void)hipFree(m.d_ckap);
+  if (m.d_cgl) (void)hipFree(m.d_cgl);
+  if (m.d_cgr) (void)hipFree(m.d_cgr);
   delete mesh;
   return FE_OK;
 }

@@ -48,6 +48,12 @@ struct KParams {
   double alpha, beta, cshift;
   double kscale;  // 1/(2 h^2): the kinetic accumulators hold 2 h^2 K~/2 X
   double dscale;  // 2 h^2: the diagonal term is stored in the same units
+  // graded meshes only (h is then the smallest cell): per 1-D cell e, the stiffness
+  // factor (h/h_e)^2 and the end-node factors of the W^{-1/2} scaling relative to the
+  // uniform tables, sqrt(2 h_e / (h_e + h_neighbour)) on the left and right
+  const double* ckap;
+  const double* cgl;
+  const double* cgr;
   double colshift[kMaxShiftCols];
 };
 
@@ -137,7 +143,43 @@ __device__ __forceinline__ void z_accumulate(int k, const CT (&cM)[NU], const CT
   }
 }
 
-template <typename T, int P, int J, int NT>
+// Graded cell: the element pair is g_i g_k (m~(i, k), kap k~ref(i, k)) with g = gl at node 0,
+// gr at node P and 1 inside. Plane k contributes g_i g_k (m~ b + kap k~ a) to output i; the
+// diagonal term is a nodal quantity and is not scaled.
+template <typename CT, int P, int CPT, int NU, int K>
+__device__ __forceinline__ void z_acc_k_graded(const CT (&cM)[NU], const CT (&cK)[NU], CT (&acc)[CPT][P + 1],
+                                               const CT (&av)[CPT], const CT (&bv)[CPT], const CT (&dv)[CPT],
+                                               CT kap, CT gl, CT gr) {
+  const CT gk = (K == 0) ? gl : ((K == P) ? gr : CT(1));
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const CT b = gk * bv[c];
+    const CT a = gk * kap * av[c];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+      CT t = cM[Canon<P>::map.slot[i][K]] * b;
+      t = fma(cK[Canon<P>::map.slot[i][K]], a, t);
+      if (i == 0) t *= gl;
+      if (i == P) t *= gr;
+      acc[c][i] += t;
+    }
+    acc[c][K] += dv[c];
+  }
+}
+
+template <typename CT, int P, int CPT, int NU, int K = 0>
+__device__ __forceinline__ void z_accumulate_graded(int k, const CT (&cM)[NU], const CT (&cK)[NU],
+                                                    CT (&acc)[CPT][P + 1], const CT (&av)[CPT], const CT (&bv)[CPT],
+                                                    const CT (&dv)[CPT], CT kap, CT gl, CT gr) {
+  if constexpr (K <= P) {
+    if (k == K)
+      z_acc_k_graded<CT, P, CPT, NU, K>(cM, cK, acc, av, bv, dv, kap, gl, gr);
+    else
+      z_accumulate_graded<CT, P, CPT, NU, K + 1>(k, cM, cK, acc, av, bv, dv, kap, gl, gr);
+  }
+}
+
+template <typename T, int P, int J, int NT, bool GR>
 __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   using CT = T;  // compute type = storage type (FP64 or FP32)
   constexpr int P1 = P + 1;
@@ -220,6 +262,24 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   }
   auto MT = [&](int i, int k) { return cM[Canon<P>::map.slot[i][k]]; };
   auto KT = [&](int i, int k) { return cK[Canon<P>::map.slot[i][k]]; };
+
+  // graded meshes: factors (kap, gl, gr) of the tile's x- and y-cells and their left
+  // neighbours in LDS, sFac[axis][q][kind] for cell e0 - 1 + q (cells outside the mesh only
+  // meet zero inputs; their entries are clamped copies)
+  constexpr int NFQ = (BEX > BEY ? BEX : BEY) + 1;
+  __shared__ CT sFac[2][NFQ][3];
+  auto cell_factors = [&](int e, CT& kap, CT& gl, CT& gr) {
+    const int ec = e < 0 ? 0 : (e >= n ? n - 1 : e);
+    kap = (CT)prm.ckap[ec];
+    gl = (CT)prm.cgl[ec];
+    gr = (CT)prm.cgr[ec];
+  };
+  if constexpr (GR) {
+    if (tid < 2 * NFQ) {
+      const int ax = tid / NFQ, q = tid % NFQ;
+      cell_factors((ax == 0 ? ex0 : ey0) - 1 + q, sFac[ax][q][0], sFac[ax][q][1], sFac[ax][q][2]);
+    }
+  }
 
   // ---- plane loader: non-redundant 16-byte chunks into registers (prefetch), then LDS.
   // The (x, y, column) part of every chunk's address is the same on all planes.
@@ -320,23 +380,56 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       CT in[2 * P + 1];
 #pragma unroll
       for (int k = 0; k <= 2 * P; ++k) in[k] = sIn[yl][exl * P + k][jj];
+      if constexpr (!GR) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        CT u1 = MT(i, 0) * in[P], u2 = KT(i, 0) * in[P];
+        for (int i = 0; i < P; ++i) {
+          CT u1 = MT(i, 0) * in[P], u2 = KT(i, 0) * in[P];
 #pragma unroll
-        for (int k = 1; k <= P; ++k) {
-          u1 = fma(MT(i, k), in[P + k], u1);
-          u2 = fma(KT(i, k), in[P + k], u2);
-        }
-        if (i == 0) {  // shared vertex: the left cell's row P as well
-#pragma unroll
-          for (int k = 0; k <= P; ++k) {
-            u1 = fma(MT(P, k), in[k], u1);
-            u2 = fma(KT(P, k), in[k], u2);
+          for (int k = 1; k <= P; ++k) {
+            u1 = fma(MT(i, k), in[P + k], u1);
+            u2 = fma(KT(i, k), in[P + k], u2);
           }
+          if (i == 0) {  // shared vertex: the left cell's row P as well
+#pragma unroll
+            for (int k = 0; k <= P; ++k) {
+              u1 = fma(MT(P, k), in[k], u1);
+              u2 = fma(KT(P, k), in[k], u2);
+            }
+          }
+          sU1[yl][exl * P + i][jj] = u1;
+          sU2[yl][exl * P + i][jj] = u2;
         }
-        sU1[yl][exl * P + i][jj] = u1;
-        sU2[yl][exl * P + i][jj] = u2;
+      } else {
+        // this cell (factors q = exl + 1) on in[P..2P], its left neighbour (q = exl) on in[0..P]
+        const CT kc = sFac[0][exl + 1][0], glc = sFac[0][exl + 1][1], grc = sFac[0][exl + 1][2];
+        const CT kl = sFac[0][exl][0], grl = sFac[0][exl][2];
+        const CT e0 = glc * in[P], eP = grc * in[2 * P];
+        const CT l0 = sFac[0][exl][1] * in[0], lP = grl * in[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          CT u1 = MT(i, 0) * e0, u2 = KT(i, 0) * e0;
+#pragma unroll
+          for (int k = 1; k < P; ++k) {
+            u1 = fma(MT(i, k), in[P + k], u1);
+            u2 = fma(KT(i, k), in[P + k], u2);
+          }
+          u1 = fma(MT(i, P), eP, u1);
+          u2 = kc * fma(KT(i, P), eP, u2);
+          if (i == 0) {  // shared vertex: the left cell's row P, with that cell's factors
+            CT w1 = MT(P, 0) * l0, w2 = KT(P, 0) * l0;
+#pragma unroll
+            for (int k = 1; k < P; ++k) {
+              w1 = fma(MT(P, k), in[k], w1);
+              w2 = fma(KT(P, k), in[k], w2);
+            }
+            w1 = fma(MT(P, P), lP, w1);
+            w2 = kl * fma(KT(P, P), lP, w2);
+            u1 = fma(glc, u1, grl * w1);
+            u2 = fma(glc, u2, grl * w2);
+          }
+          sU1[yl][exl * P + i][jj] = u1;
+          sU2[yl][exl * P + i][jj] = u2;
+        }
       }
       if (yl >= P && yl < P + BY) {
         const int j = j0 + jj;
@@ -359,26 +452,63 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
         a1[k] = sU1[eyl * P + k][xl][jj];
         a2[k] = sU2[eyl * P + k][xl][jj];
       }
+      if constexpr (!GR) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        CT A = MT(i, 0) * a1[P], B = MT(i, 0) * a2[P];
-        B = fma(KT(i, 0), a1[P], B);
+        for (int i = 0; i < P; ++i) {
+          CT A = MT(i, 0) * a1[P], B = MT(i, 0) * a2[P];
+          B = fma(KT(i, 0), a1[P], B);
 #pragma unroll
-        for (int k = 1; k <= P; ++k) {
-          A = fma(MT(i, k), a1[P + k], A);
-          B = fma(MT(i, k), a2[P + k], B);
-          B = fma(KT(i, k), a1[P + k], B);
-        }
-        if (i == 0) {
-#pragma unroll
-          for (int k = 0; k <= P; ++k) {
-            A = fma(MT(P, k), a1[k], A);
-            B = fma(MT(P, k), a2[k], B);
-            B = fma(KT(P, k), a1[k], B);
+          for (int k = 1; k <= P; ++k) {
+            A = fma(MT(i, k), a1[P + k], A);
+            B = fma(MT(i, k), a2[P + k], B);
+            B = fma(KT(i, k), a1[P + k], B);
           }
+          if (i == 0) {
+#pragma unroll
+            for (int k = 0; k <= P; ++k) {
+              A = fma(MT(P, k), a1[k], A);
+              B = fma(MT(P, k), a2[k], B);
+              B = fma(KT(P, k), a1[k], B);
+            }
+          }
+          sA[eyl * P + i][xl][jj] = A;
+          sB[eyl * P + i][xl][jj] = B;
         }
-        sA[eyl * P + i][xl][jj] = A;
-        sB[eyl * P + i][xl][jj] = B;
+      } else {
+        const CT kc = sFac[1][eyl + 1][0], glc = sFac[1][eyl + 1][1], grc = sFac[1][eyl + 1][2];
+        const CT kl = sFac[1][eyl][0], gll = sFac[1][eyl][1], grl = sFac[1][eyl][2];
+        const CT p0 = glc * a1[P], pP = grc * a1[2 * P], q0 = glc * a2[P], qP = grc * a2[2 * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          CT A = MT(i, 0) * p0, Bm = MT(i, 0) * q0, Bk = KT(i, 0) * p0;
+#pragma unroll
+          for (int k = 1; k < P; ++k) {
+            A = fma(MT(i, k), a1[P + k], A);
+            Bm = fma(MT(i, k), a2[P + k], Bm);
+            Bk = fma(KT(i, k), a1[P + k], Bk);
+          }
+          A = fma(MT(i, P), pP, A);
+          Bm = fma(MT(i, P), qP, Bm);
+          Bk = fma(KT(i, P), pP, Bk);
+          CT B = fma(kc, Bk, Bm);
+          if (i == 0) {
+            const CT r0 = gll * a1[0], rP = grl * a1[P], s0 = gll * a2[0], sP = grl * a2[P];
+            CT Al = MT(P, 0) * r0, Bml = MT(P, 0) * s0, Bkl = KT(P, 0) * r0;
+#pragma unroll
+            for (int k = 1; k < P; ++k) {
+              Al = fma(MT(P, k), a1[k], Al);
+              Bml = fma(MT(P, k), a2[k], Bml);
+              Bkl = fma(KT(P, k), a1[k], Bkl);
+            }
+            Al = fma(MT(P, P), rP, Al);
+            Bml = fma(MT(P, P), sP, Bml);
+            Bkl = fma(KT(P, P), rP, Bkl);
+            A = fma(glc, A, grl * Al);
+            B = fma(glc, B, grl * fma(kl, Bkl, Bml));
+          }
+          sA[eyl * P + i][xl][jj] = A;
+          sB[eyl * P + i][xl][jj] = B;
+        }
       }
     }
     // the raw plane and potential were last read by this plane's x-pass (before the barrier above)
@@ -402,7 +532,16 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       bv[c] = sB[yl][xl][jj];
       dv[c] = sD[buf][yl][xl][jj];
     }
-    z_accumulate<CT, P, CPT, NU>(k, cM, cK, acc, av, bv, dv);
+    // graded meshes: factors of the current z-cell (plane gz is its node k) and of the next
+    CT zk = 1, zl = 1, zr = 1, nk = 1, nl = 1, nr = 1;
+    if constexpr (GR) {
+      const int ezc = (rel == 0) ? ezs : ezs + (rel - 1) / P;
+      cell_factors(ezc, zk, zl, zr);
+      cell_factors(ezc + 1, nk, nl, nr);
+      z_accumulate_graded<CT, P, CPT, NU>(k, cM, cK, acc, av, bv, dv, zk, zl, zr);
+    } else {
+      z_accumulate<CT, P, CPT, NU>(k, cM, cK, acc, av, bv, dv);
+    }
     if (k == P) {
       // cell ez complete: planes ez P + i, i < P, are final
       const int ez = (rel - 1) / P + ezs;
@@ -435,12 +574,27 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
         }
       }
       // this vertex plane is also node 0 of the next cell
+      if constexpr (!GR) {
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const CT carry = acc[c][P];
+        for (int c = 0; c < CPT; ++c) {
+          const CT carry = acc[c][P];
 #pragma unroll
-        for (int i = 0; i <= P; ++i)
-          acc[c][i] = fma(KT(i, 0), av[c], fma(MT(i, 0), bv[c], i == 0 ? carry : CT(0)));
+          for (int i = 0; i <= P; ++i)
+            acc[c][i] = fma(KT(i, 0), av[c], fma(MT(i, 0), bv[c], i == 0 ? carry : CT(0)));
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const CT carry = acc[c][P];
+          const CT b = nl * bv[c], a = nl * nk * av[c];
+#pragma unroll
+          for (int i = 0; i <= P; ++i) {
+            CT t = fma(KT(i, 0), a, MT(i, 0) * b);
+            if (i == 0) t *= nl;
+            if (i == P) t *= nr;
+            acc[c][i] = (i == 0) ? carry + t : t;
+          }
+        }
       }
     }
     buf ^= 1;
@@ -729,7 +883,7 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
 
 namespace {
 
-template <typename T, int P, int J>
+template <typename T, int P, int J, bool GR = false>
 fe_status launch_typed(const Mesh& m, KParams& prm, hipStream_t s) {
   constexpr int NT = 256;
   prm.tiles_x = (m.n + TileShape<P, T>::BEX - 1) / TileShape<P, T>::BEX;
@@ -746,7 +900,7 @@ fe_status launch_typed(const Mesh& m, KParams& prm, hipStream_t s) {
   prm.zsegs = zsegs;
   const long long grid = base * zsegs;
   if (grid > 0x7fffffffLL) return fail(FE_EINVAL, "ks_apply: problem too large for one launch");
-  hipLaunchKernelGGL((ks_apply_kernel<T, P, J, NT>), dim3((unsigned)grid), dim3(NT), 0, s, prm);
+  hipLaunchKernelGGL((ks_apply_kernel<T, P, J, NT, GR>), dim3((unsigned)grid), dim3(NT), 0, s, prm);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -772,8 +926,26 @@ fe_status launch_yz(const Mesh& m, KParams& prm, hipStream_t s) {
   return FE_OK;
 }
 
+// graded meshes: the separate-pass kernel with per-cell factors, every order and precision
+template <typename T, int J>
+fe_status launch_p_graded(const Mesh& m, KParams& prm, hipStream_t s) {
+  switch (m.p) {
+    case 1: return launch_typed<T, 1, J, true>(m, prm, s);
+    case 2: return launch_typed<T, 2, J, true>(m, prm, s);
+    case 3: return launch_typed<T, 3, J, true>(m, prm, s);
+    case 4: return launch_typed<T, 4, J, true>(m, prm, s);
+    case 5: return launch_typed<T, 5, J, true>(m, prm, s);
+    case 6: return launch_typed<T, 6, J, true>(m, prm, s);
+    case 7: return launch_typed<T, 7, J, true>(m, prm, s);
+    case 8: return launch_typed<T, 8, J, true>(m, prm, s);
+    default: return fail(FE_EINVAL, "ks_apply: unsupported order p");
+  }
+}
+
 template <typename T, int J>
 fe_status launch_p(const Mesh& m, KParams& prm, hipStream_t s) {
+  // (FP32 graded: 8-column chunks; 16 would cost the second wave per SIMD at p = 5)
+  if (m.graded) return launch_p_graded<T, (sizeof(T) == 4 ? 8 : J)>(m, prm, s);
   switch (m.p) {
     case 1: return launch_typed<T, 1, J>(m, prm, s);
     case 2: return launch_typed<T, 2, J>(m, prm, s);
@@ -880,6 +1052,9 @@ static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec
   prm.cshift = a.cshift;
   prm.kscale = 0.5 / (m.h * m.h);
   prm.dscale = 2.0 * m.h * m.h;
+  prm.ckap = m.d_ckap;
+  prm.cgl = m.d_cgl;
+  prm.cgr = m.d_cgr;
   if (a.colshift) {
     if (a.nv > kMaxShiftCols) return fail(FE_EINVAL, "ks_apply: per-column shifts limited to 256 columns");
     prm.has_colshift = 1;

@@ -32,6 +32,14 @@ struct Mesh {
   double* d_w1 = nullptr;
   double* d_kd1 = nullptr;
   double* d_md1 = nullptr;
+  // graded meshes (cells of different widths; h above is then the smallest): per 1-D
+  // cell, the stiffness factor (h/h_e)^2 and the end-node factors of the W1^{-1/2}
+  // scaling relative to the uniform tables (device copies, n each)
+  bool graded = false;
+  std::vector<double> cell_h;
+  double* d_ckap = nullptr;
+  double* d_cgl = nullptr;
+  double* d_cgr = nullptr;
 };
 
 // the tables behind a mesh handle (NULL for a NULL handle)
