@@ -17,6 +17,10 @@ finite-element inverse DFT (Sec. 2 and Sec. 3.2):
                 (Sec. 3.2.2, Eqs. 23-24) by their plain definitions.
 * ``vxcmesh`` — the XC potential on its own linear mesh (Eq. 14): the prolongation
                 to the orbital nodes and the gradient's transpose (Eq. 22).
+* ``hartree`` — the Hartree potential by a finite-element Poisson solve with the
+                monopole split off in closed form (the Hamiltonian of Sec. 2).
+* ``xcinit``  — the initial guess of Eq. 25 (Slater exchange, PW92 correlation,
+                Fermi-Amaldi tail).
 * ``thermal`` — finite temperature: Fermi-Dirac occupancy and mu (Eqs. 4, 5), the
                 adjoint of each degenerate block with Eqs. 8-9 (Sec. 2, Sec. 3.2.2),
                 the gradient of Eq. 10.
