@@ -79,7 +79,8 @@ typedef enum {
   FE_OP_ADJOINT_SOLVE = 3,
   FE_OP_LOSS_GRAD = 4,
   FE_OP_EIGENSOLVE = 5,
-  FE_OP_ALONG_PSI = 6
+  FE_OP_ALONG_PSI = 6,
+  FE_OP_POISSON = 7
 } fe_op;
 
 /* ------------------------------------------------------------------ mesh --
@@ -119,7 +120,7 @@ fe_status fe_mesh_destroy(fe_mesh mesh);
 
 /* Bytes of device work buffer an operation needs for a block of nv columns
  * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD, nv = n for
- * FE_OP_ALONG_PSI). 0 on bad input. */
+ * FE_OP_ALONG_PSI, nv = 1 for FE_OP_POISSON). 0 on bad input. */
 size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec);
 
 const char* fe_last_error(void);
@@ -237,6 +238,35 @@ fe_status vxc_prolong(vxc_mesh vm, const double* u, const double* base, double* 
  * reproducible). The passes use two intermediate arrays owned by the handle, so
  * calls on one handle must not overlap (one stream at a time). Asynchronous. */
 fe_status vxc_restrict(vxc_mesh vm, const double* g, double* f, void* stream);
+
+/* --------------------------------------------------------- poisson_solve --
+ * The Hartree potential v_H = int rho(r') / |r - r'| dr' of a density (part of the
+ * Hamiltonian of Sec. 2; its Fermi-Amaldi scaling enters Eq. 25), from
+ * -lap phi = 4 pi rho on the orbital mesh with zero values on the box and the
+ * GLL-lumped right-hand side: (K~/2) phi~ = 2 pi W^{1/2} rho', phi = W^{-1/2} phi~.
+ * With sigma > 0 the monopole is split off: Q = sum_a W_a rho_a, c its centroid,
+ * rho' = rho - Q g_sigma(r - c) (normalised Gaussian), and the Gaussian's potential
+ * Q erf(|r - c| / (sqrt(2) sigma)) / |r - c| is added in closed form (rho' has no
+ * charge and no dipole about c). sigma = 0 solves for rho itself.
+ * Conjugate gradients with the kinetic diagonal as preconditioner, each product
+ * one ks_apply of the same stiffness with a zero potential; stops when
+ * ||b - A x|| <= tol ||b|| or after maxit products.
+ *   rho, phi: N_f device doubles (phi written, also on FE_ENOCONV). iters_h,
+ *   relres_h, charge_h (Q): host outputs, each nullable.
+ * work: fe_workspace_bytes(FE_OP_POISSON, 1). Synchronises the stream.
+ * Errors: FE_EINVAL (NULL pointers, tol <= 0, maxit < 1, sigma < 0), FE_ENOCONV. */
+fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma, double* phi, double tol, int maxit,
+                        int* iters_h, double* relres_h, double* charge_h, void* work, void* stream);
+
+/* ------------------------------------------------------ xc_initial_guess --
+ * Eq. 25: v = f v0 + (1 - f) alpha v_FA node by node, f = rho / (rho + tau),
+ * v_FA = -v_H / n_elec (Fermi-Amaldi), v0 = Slater exchange -(3 rho / pi)^{1/3}
+ * + Perdew-Wang 1992 correlation of the unpolarised gas (v0 = 0 where
+ * rho <= 1e-30). The paper's other choice of exchange (LB94) needs density
+ * gradients and is not provided. rho, v_h, v: n device doubles. Asynchronous.
+ * Errors: FE_EINVAL (NULL pointers, n < 0, n_elec <= 0, tau <= 0). */
+fe_status xc_initial_guess(const double* rho, const double* v_h, int64_t n, double n_elec, double tau,
+                           double alpha, double* v, void* stream);
 
 /* ----------------------------------------------------- fermi_occupations --
  * Finite-temperature occupations (Eq. 4's Fermi-Dirac occupancy, Eq. 5):

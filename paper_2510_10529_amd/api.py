@@ -302,3 +302,34 @@ def adjoint_along_psi(mesh: Mesh, Psi, eps, mu: float, kT: float, rho, rho_data,
                                        float(smax), _ptr(rho), _ptr(rho_data), _ptr(Q), C.byref(eta), Ch,
                                        _ptr(work), _stream()), "adjoint_along_psi")
     return eta.value, list(Ch)
+
+
+@dataclass
+class PoissonResult:
+    iters: int
+    relres: float
+    charge: float
+    status: int
+
+
+def poisson_solve(mesh: Mesh, rho, sigma: float = 1.0, tol: float = 1e-12, maxit: int = 20000, phi=None,
+                  work=None, allow=()) -> tuple:
+    """Hartree potential of rho on the mesh's free nodes (monopole split off with width sigma)."""
+    if phi is None:
+        phi = torch.empty_like(rho)
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_POISSON, 1), rho.device)
+    it, rel, q = C.c_int(), C.c_double(), C.c_double()
+    st = L.load().poisson_solve(mesh.handle, _ptr(rho), float(sigma), _ptr(phi), float(tol), int(maxit),
+                                C.byref(it), C.byref(rel), C.byref(q), _ptr(work), _stream())
+    L.check(st, "poisson_solve", allow=allow)
+    return phi, PoissonResult(it.value, rel.value, q.value, st)
+
+
+def xc_initial_guess(rho, v_h, n_elec: float, tau: float = 1e-2, alpha: float = 1.0, out=None):
+    """Eq. 25 with Slater exchange + PW92 correlation and the Fermi-Amaldi tail."""
+    if out is None:
+        out = torch.empty_like(rho)
+    L.check(L.load().xc_initial_guess(_ptr(rho), _ptr(v_h), rho.numel(), float(n_elec), float(tau), float(alpha),
+                                      _ptr(out), _stream()), "xc_initial_guess")
+    return out

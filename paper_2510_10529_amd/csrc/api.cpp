@@ -657,6 +657,7 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
       bp.take<double>(project_work_bytes(m.nf, nv, nv) / sizeof(double) + 1);
       return bp.off;
     case FE_OP_ALONG_PSI: return along_psi_work_bytes(m.nf, nv);
+    case FE_OP_POISSON: return poisson_work_bytes(m.nf);
     default: return 0;
   }
 }

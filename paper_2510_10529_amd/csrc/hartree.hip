@@ -1,0 +1,243 @@
+// Physics front end (gfx950): the Hartree potential of a density by a finite-element
+// Poisson solve on the orbital mesh, and the initial guess of Eq. 25.
+//
+// Hartree: -lap v_H = 4 pi rho with zero values on the box and the GLL-lumped
+// right-hand side, in standard form (K~/2) phi~ = 2 pi W^{1/2} rho, phi = W^{-1/2} phi~.
+// The monopole is split off first: Q = sum_a W_a rho_a and the centroid c, then
+// rho' = rho - Q g_s(r - c) with the normalised Gaussian g_s, whose potential
+// Q erf(|r - c| / (sqrt(2) s)) / |r - c| is added in closed form; rho' has no charge
+// and no dipole about c, so the box's zero boundary values cost only its quadrupole
+// and higher terms. The linear system is solved by conjugate gradients with the
+// kinetic diagonal as preconditioner, each product one ks_apply with a zero
+// potential (the same matrix-free stiffness as the Kohn-Sham operator).
+//
+// Initial guess: v = f v0 + (1 - f) alpha (-v_H / N_e), f = rho / (rho + tau),
+// v0 = Slater exchange -(3 rho / pi)^{1/3} + Perdew-Wang 1992 correlation of the
+// unpolarised gas, evaluated node by node.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+#include "krylov.h"
+
+namespace invdft {
+namespace {
+
+constexpr int kMomentsThreads = 256;
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ void node_of(long long a, int n1, int& ix, int& iy, int& iz) {
+  ix = (int)(a % n1);
+  iy = (int)((a / n1) % n1);
+  iz = (int)(a / ((long long)n1 * n1));
+}
+
+// per-block partial sums of W rho, W rho x, W rho y, W rho z (fixed-order tree in LDS)
+__global__ __launch_bounds__(kMomentsThreads) void moments_partial_kernel(const double* __restrict__ x1,
+                                                                          const double* __restrict__ w1, int n1,
+                                                                          long long nf, const double* __restrict__ rho,
+                                                                          long long per_blk,
+                                                                          double* __restrict__ partial) {
+  __shared__ double red[4][kMomentsThreads];
+  const long long b0 = (long long)blockIdx.x * per_blk;
+  const long long b1 = min(nf, b0 + per_blk);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long a = b0 + threadIdx.x; a < b1; a += kMomentsThreads) {
+    int ix, iy, iz;
+    node_of(a, n1, ix, iy, iz);
+    const double q = w1[ix] * w1[iy] * w1[iz] * rho[a];
+    s[0] += q;
+    s[1] += q * x1[ix];
+    s[2] += q * x1[iy];
+    s[3] += q * x1[iz];
+  }
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = kMomentsThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[(long long)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct Monopole {
+  double Q, cx, cy, cz, s;  // s <= 0: no split
+};
+
+// b = 2 pi W^{1/2} (rho - Q g_s(r - c))
+__global__ void poisson_rhs_kernel(const double* __restrict__ x1, const double* __restrict__ w1, int n1, long long nf,
+                                   const double* __restrict__ rho, Monopole mp, double* __restrict__ b) {
+  const double norm = mp.s > 0 ? 1.0 / (2.0 * kPi * mp.s * mp.s * sqrt(2.0 * kPi * mp.s * mp.s)) : 0.0;
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_of(a, n1, ix, iy, iz);
+    double r = rho[a];
+    if (mp.s > 0) {
+      const double dx = x1[ix] - mp.cx, dy = x1[iy] - mp.cy, dz = x1[iz] - mp.cz;
+      r -= mp.Q * norm * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * mp.s * mp.s));
+    }
+    b[a] = 2.0 * kPi * sqrt(w1[ix] * w1[iy] * w1[iz]) * r;
+  }
+}
+
+// phi = W^{-1/2} x + Q erf(|r - c| / (sqrt(2) s)) / |r - c|
+__global__ void poisson_finish_kernel(const double* __restrict__ x1, const double* __restrict__ w1, int n1,
+                                      long long nf, const double* __restrict__ xt, Monopole mp,
+                                      double* __restrict__ phi) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    node_of(a, n1, ix, iy, iz);
+    double v = xt[a] / sqrt(w1[ix] * w1[iy] * w1[iz]);
+    if (mp.s > 0) {
+      const double dx = x1[ix] - mp.cx, dy = x1[iy] - mp.cy, dz = x1[iz] - mp.cz;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      v += mp.Q * (r < 1e-8 * mp.s ? sqrt(2.0 / kPi) / mp.s : erf(r / (sqrt(2.0) * mp.s)) / r);
+    }
+    phi[a] = v;
+  }
+}
+
+// Perdew-Wang 1992, unpolarised: e_c(r_s) and v_c = e_c - (r_s/3) de_c/dr_s
+__device__ __forceinline__ double pw92_vc(double rho) {
+  const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double rs = cbrt(3.0 / (4.0 * kPi * rho));
+  const double s = sqrt(rs);
+  const double q = 2.0 * A * (b1 * s + b2 * rs + b3 * rs * s + b4 * rs * rs);
+  const double dq = A * (b1 / s + 2.0 * b2 + 3.0 * b3 * s + 4.0 * b4 * rs);
+  const double lg = log1p(1.0 / q);
+  const double ec = -2.0 * A * (1.0 + a1 * rs) * lg;
+  const double dec = -2.0 * A * a1 * lg + 2.0 * A * (1.0 + a1 * rs) * dq / (q * q + q);
+  return ec - rs / 3.0 * dec;
+}
+
+__global__ void xc_init_kernel(const double* __restrict__ rho, const double* __restrict__ vh, long long n,
+                               double n_elec, double tau, double alpha, double* __restrict__ v) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (long long)gridDim.x * blockDim.x) {
+    const double r = rho[a];
+    const double f = r / (r + tau);
+    const double v0 = r > 1e-30 ? -cbrt(3.0 * r / kPi) + pw92_vc(r) : 0.0;
+    v[a] = f * v0 + (1.0 - f) * alpha * (-vh[a] / n_elec);
+  }
+}
+
+unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192)); }
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t poisson_work_bytes(int64_t nf) { return 7 * round256((size_t)nf * sizeof(double)) + round256(8192 * 8) + 256; }
+
+}  // namespace invdft
+
+using namespace invdft;
+
+extern "C" fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma, double* phi, double tol, int maxit,
+                                   int* iters_h, double* relres_h, double* charge_h, void* work, void* stream) {
+  const Mesh* mp = mesh_tables(mesh);
+  if (!mp) return fail(FE_EINVAL, "mesh handle is NULL");
+  if (!rho || !phi || !work) return fail(FE_EINVAL, "poisson_solve: NULL argument");
+  if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "poisson_solve: tol > 0 and maxit >= 1 required");
+  if (!(sigma >= 0.0)) return fail(FE_EINVAL, "poisson_solve: sigma must be >= 0");
+  const Mesh& m = *mp;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long nf = m.nf;
+  char* w = static_cast<char*>(work);
+  const size_t vb = round256((size_t)nf * sizeof(double));
+  double* x = reinterpret_cast<double*>(w);
+  double* r = reinterpret_cast<double*>(w + vb);
+  double* z = reinterpret_cast<double*>(w + 2 * vb);
+  double* p = reinterpret_cast<double*>(w + 3 * vb);
+  double* q = reinterpret_cast<double*>(w + 4 * vb);
+  double* dinv = reinterpret_cast<double*>(w + 5 * vb);
+  double* vzero = reinterpret_cast<double*>(w + 6 * vb);
+  double* scratch = reinterpret_cast<double*>(w + 7 * vb);   // 1024 partials + scalars
+  double* scal = scratch + 8000;
+  fe_status st;
+  // charge and centroid: per-block partials, summed on the host in block order
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((nf + 4095) / 4096, 1024));
+  const long long per = (nf + nblk - 1) / nblk;
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(nblk), dim3(kMomentsThreads), 0, s, m.d_x1, m.d_w1, m.n1, nf, rho,
+                     per, scratch);
+  INVDFT_HIP(hipGetLastError());
+  std::vector<double> part((size_t)nblk * 4);
+  INVDFT_HIP(hipMemcpyAsync(part.data(), scratch, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  double mom[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int bk = 0; bk < nblk; ++bk)
+    for (int c = 0; c < 4; ++c) mom[c] += part[(size_t)bk * 4 + c];
+  Monopole mono{mom[0], 0.0, 0.0, 0.0, 0.0};
+  if (sigma > 0.0 && mom[0] != 0.0) {
+    mono.cx = mom[1] / mom[0];
+    mono.cy = mom[2] / mom[0];
+    mono.cz = mom[3] / mom[0];
+    mono.s = sigma;
+  }
+  if (charge_h) *charge_h = mom[0];
+  // r = b, x = 0, z = D^{-1} r, p = z
+  hipLaunchKernelGGL(poisson_rhs_kernel, dim3(grid_for(nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.n1, nf, rho, mono, r);
+  INVDFT_HIP(hipGetLastError());
+  if ((st = fill(x, 0.0, nf, s)) != FE_OK) return st;
+  if ((st = fill(vzero, 0.0, nf, s)) != FE_OK) return st;
+  if ((st = k_dinv(m, dinv, s)) != FE_OK) return st;
+  auto dot = [&](const double* a, const double* b, double* out_h) -> fe_status {
+    fe_status e = dot1(a, b, nf, scal, scratch, s);
+    if (e != FE_OK) return e;
+    INVDFT_HIP(hipMemcpyAsync(out_h, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    INVDFT_HIP(hipStreamSynchronize(s));
+    return FE_OK;
+  };
+  double bb = 0.0, rz = 0.0, rr = 0.0, pq = 0.0;
+  if ((st = dot(r, r, &bb)) != FE_OK) return st;
+  if ((st = k_precond<double>(r, dinv, 1, nf, z, s)) != FE_OK) return st;
+  if ((st = copy_bytes(z, p, (size_t)nf * sizeof(double), s)) != FE_OK) return st;
+  if ((st = dot(r, z, &rz)) != FE_OK) return st;
+  ApplyArgs aa{};
+  aa.X = p;
+  aa.Y = q;
+  aa.v = vzero;
+  aa.nv = 1;
+  aa.ld = 1;
+  aa.alpha = 1.0;
+  int it = 0;
+  double rel = bb > 0.0 ? 1.0 : 0.0;
+  while (bb > 0.0 && it < maxit) {
+    if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;   // q = (K~/2) p
+    if ((st = dot(p, q, &pq)) != FE_OK) return st;
+    const double alpha = rz / pq;
+    if ((st = axpby(alpha, p, 1.0, x, nf, s)) != FE_OK) return st;
+    if ((st = axpby(-alpha, q, 1.0, r, nf, s)) != FE_OK) return st;
+    ++it;
+    if ((st = dot(r, r, &rr)) != FE_OK) return st;
+    rel = std::sqrt(rr / bb);
+    if (rel <= tol) break;
+    if ((st = k_precond<double>(r, dinv, 1, nf, z, s)) != FE_OK) return st;
+    double rz_new = 0.0;
+    if ((st = dot(r, z, &rz_new)) != FE_OK) return st;
+    if ((st = axpby(1.0, z, rz_new / rz, p, nf, s)) != FE_OK) return st;   // p = z + beta p
+    rz = rz_new;
+  }
+  hipLaunchKernelGGL(poisson_finish_kernel, dim3(grid_for(nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.n1, nf, x, mono,
+                     phi);
+  INVDFT_HIP(hipGetLastError());
+  INVDFT_HIP(hipStreamSynchronize(s));
+  if (iters_h) *iters_h = it;
+  if (relres_h) *relres_h = rel;
+  if (rel > tol) return fail(FE_ENOCONV, "poisson_solve: tolerance not reached in maxit iterations");
+  return FE_OK;
+}
+
+extern "C" fe_status xc_initial_guess(const double* rho, const double* v_h, int64_t n, double n_elec, double tau,
+                                      double alpha, double* v, void* stream) {
+  if (!rho || !v_h || !v) return fail(FE_EINVAL, "xc_initial_guess: NULL argument");
+  if (n < 0 || !(n_elec > 0.0) || !(tau > 0.0)) return fail(FE_EINVAL, "xc_initial_guess: n >= 0, n_elec > 0, tau > 0");
+  if (n == 0) return FE_OK;
+  hipLaunchKernelGGL(xc_init_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), rho, v_h,
+                     (long long)n, n_elec, tau, alpha, v);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}

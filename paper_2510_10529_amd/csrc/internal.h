@@ -94,6 +94,7 @@ fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, 
 fe_status gram_weighted(const double* X, int ld, const double* wa, const double* wb, int64_t N, int n, double* out,
                         void* work, hipStream_t s);
 size_t along_psi_work_bytes(int64_t N, int n);
+size_t poisson_work_bytes(int64_t nf);
 // Y += X C over N rows (X: N x nin, C: nin x nout row-major on the device, Y: N x nout).
 fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* Y, int ldy,
                      hipStream_t s);
