@@ -35,7 +35,11 @@ bohr on the inner cube [-L/2, L/2]^3, growing by 1.35 towards the box (for workl
 and H = 0.6: 36 cells per axis, 5.7 M free nodes, against 40 cells of 0.8 bohr and
 7.9 M nodes for the uniform mesh).
 
+With --frontend the set-up also times the physics front end on the target density: the
+Hartree potential by the finite-element Poisson solve and the initial guess of Eq. 25.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0] [--vxc-h 0] [--graded 0]
+                       [--frontend]
 """
 from __future__ import annotations
 
@@ -148,6 +152,8 @@ def main():
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kT", type=float, default=0.0, help="k_B T in Ha (0: zero temperature)")
+    ap.add_argument("--frontend", action="store_true",
+                    help="time the Hartree solve and the initial guess on the target density")
     ap.add_argument("--graded", type=float, default=0.0,
                     help="inner cell size of a graded orbital mesh (0: the workload's uniform mesh)")
     ap.add_argument("--vxc-h", type=float, default=0.0,
@@ -235,6 +241,21 @@ def main():
     log(f"set-up (target density + initial orbitals) {time.perf_counter() - t0:.1f} s, "
         f"target passes {target_passes}" + (f", {target_incl} orbitals enter" if kT > 0 else ""))
     del X0
+
+    fe_info = {}
+    if args.frontend:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v_h, pres = api.poisson_solve(mesh, rho_d, sigma=1.0, tol=1e-10)
+        t1 = time.perf_counter()
+        v_init = api.xc_initial_guess(rho_d, v_h, float(wl.n_elec))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fe_info = {"hartree_s": t1 - t0, "hartree_cg_iters": pres.iters, "hartree_relres": pres.relres,
+                   "hartree_charge": pres.charge, "initial_guess_ms": 1000 * (t2 - t1)}
+        log(f"front end: Hartree {t1 - t0:.2f} s ({pres.iters} CG iterations, charge {pres.charge:.10f}), "
+            f"initial guess {1000 * (t2 - t1):.2f} ms")
+        del v_h, v_init
 
     vxc = None
     vxc_info = {}
@@ -366,6 +387,7 @@ def main():
         "ks_apply_ms_f64": ms64,
         **out_extra,
         **vxc_info,
+        **fe_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
