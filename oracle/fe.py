@@ -117,11 +117,12 @@ def mesh1d(p: int, n: int, L: float, breaks: np.ndarray | None = None) -> Mesh1D
     """
     if breaks is None:
         t = -L + (2.0 * L / n) * np.arange(n + 1)
+        hs = np.full(n, 2.0 * L / n)          # exactly 2L/n: differences of t would differ in the last bits
     else:
         t = np.asarray(breaks, dtype=np.float64)
         n = t.size - 1
         L = 0.5 * (t[-1] - t[0])
-    hs = np.diff(t)
+        hs = np.diff(t)
     Kh, Mh, xi, wg = reference_matrices(p)
     N = p * n + 1
     K = np.zeros((N, N))
