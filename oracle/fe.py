@@ -270,6 +270,37 @@ def hamiltonian_rows(mesh: Mesh3D, v: np.ndarray, X: np.ndarray, rows, shift=Non
     return out
 
 
+def derivative_1d(mesh: Mesh3D) -> np.ndarray:
+    """D1 (n1 x n1): the derivative of the order-p interpolant at the free 1-D nodes, from the
+    Lagrange derivatives of each cell (Eq. 12) with the two one-sided values averaged at a
+    vertex shared by two cells; the Dirichlet end values are 0."""
+    m = mesh.m1
+    p, n = m.p, m.n
+    xi, _ = gll_nodes_weights(p)
+    Dh = lagrange_derivs(xi, xi)                      # Dh[j, k] = N_k'(xi_j)
+    N = p * n + 1
+    hs = np.diff(m.x_all[::p])                        # cell widths from the vertex coordinates
+    D = np.zeros((N, N))
+    cnt = np.zeros(N)
+    for e in range(n):
+        idx = e * p + np.arange(p + 1)
+        D[np.ix_(idx, idx)] += (2.0 / hs[e]) * Dh
+        cnt[idx] += 1
+    D /= cnt[:, None]
+    return D[1:N - 1, 1:N - 1].copy()
+
+
+def nodal_gradient(mesh: Mesh3D, f: np.ndarray) -> np.ndarray:
+    """(N_f, 3) gradient of a nodal field at the free nodes, axis by axis with derivative_1d."""
+    n1 = mesh.n1
+    D = derivative_1d(mesh)
+    T = np.asarray(f, dtype=np.float64).reshape(n1, n1, n1)      # [z, y, x]
+    gx = np.einsum("ik,zyk->zyi", D, T)
+    gy = np.einsum("ik,zkx->zix", D, T)
+    gz = np.einsum("ik,kyx->iyx", D, T)
+    return np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+
+
 def kinetic_diag(mesh: Mesh3D) -> np.ndarray:
     """Diagonal of K~/2: the preconditioner of Sec. 3.2.2 (inverse diagonal of the
     kinetic, i.e. negative-Laplacian, part)."""

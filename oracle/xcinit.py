@@ -49,9 +49,25 @@ def pw92_potential(rho: np.ndarray) -> np.ndarray:
     return np.where(rho > RHO_MIN, ec - rs / 3.0 * dec, 0.0)
 
 
+LB94_BETA = 0.05
+
+
+def lb94_exchange(rho: np.ndarray, grad_norm: np.ndarray) -> np.ndarray:
+    """van Leeuwen-Baerends exchange of the unpolarised gas, per spin density rho_s = rho / 2:
+    v_x = v_x^LDA(rho) - beta rho_s^{1/3} x^2 / (1 + 3 beta x asinh x), x = |grad rho_s| / rho_s^{4/3}."""
+    r = np.maximum(rho, 0.0)
+    ok = r > RHO_MIN
+    rs = np.where(ok, 0.5 * r, 1.0)
+    x = np.where(ok, 0.5 * grad_norm / rs ** (4.0 / 3.0), 0.0)
+    corr = LB94_BETA * np.cbrt(rs) * x * x / (1.0 + 3.0 * LB94_BETA * x * np.arcsinh(x))
+    return np.where(ok, slater_exchange(rho) - corr, 0.0)
+
+
 def initial_guess(rho: np.ndarray, v_h: np.ndarray, n_elec: float, tau: float = 1e-2,
-                  alpha: float = 1.0) -> np.ndarray:
-    """Eq. 25 with v_0 = Slater exchange + PW92 correlation."""
+                  alpha: float = 1.0, grad_norm: np.ndarray | None = None) -> np.ndarray:
+    """Eq. 25 with v_0 = Slater exchange + PW92 correlation, or LB94 exchange + PW92 when the
+    density's gradient norm is given."""
     f = rho / (rho + tau)
-    v0 = slater_exchange(rho) + pw92_potential(rho)
+    vx = slater_exchange(rho) if grad_norm is None else lb94_exchange(rho, grad_norm)
+    v0 = vx + pw92_potential(rho)
     return f * v0 + (1.0 - f) * alpha * (-v_h / n_elec)

@@ -82,3 +82,38 @@ def test_initial_guess_blend():
     v0 = xc.slater_exchange(rho) + xc.pw92_potential(rho)
     np.testing.assert_allclose(v, f * v0 - (1 - f) * vh / 10.0, rtol=1e-14)
     assert abs(v[3] - v0[3]) < 1e-2 * abs(v0[3])                   # dense: v_0
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_nodal_gradient_exact_for_interpolated_polynomials(p):
+    """A field of degree <= p per axis that vanishes on the box is its own interpolant: the
+    recovered gradient is exact, also at vertices shared by two cells (both one-sided values
+    agree) and on graded cells."""
+    from synth import vxc_vertices
+    a = (lambda t: 4 - t * t, lambda t: -2 * t)                    # degree 2, zero at +-2
+    b = (lambda t: (4 - t * t) * (1 + t), lambda t: -2 * t * (1 + t) + (4 - t * t))   # degree 3
+    for m in (fe.mesh3d(p, 3, 2.0), fe.mesh3d_graded(p, vxc_vertices(2.0, 0.5, 0.6, 1.8))):
+        X = m.coords()
+        fx, fy, fz = a, (b if p >= 3 else a), (b if p >= 3 else a)
+        x, y, z = X[:, 0], X[:, 1], X[:, 2]
+        f = fx[0](x) * fy[0](y) * fz[0](z)
+        g = np.stack([fx[1](x) * fy[0](y) * fz[0](z), fx[0](x) * fy[1](y) * fz[0](z),
+                      fx[0](x) * fy[0](y) * fz[1](z)], axis=1)
+        np.testing.assert_allclose(fe.nodal_gradient(m, f), g, rtol=0, atol=1e-11 * np.abs(g).max())
+
+
+def test_lb94_decays_as_minus_one_over_r():
+    """For an exponential density the LB94 potential tends to -1/r (its design property)."""
+    # rho = e^{-a r} / pi: x_s = a rho_s^{-1/3}, and for large x the correction tends to
+    # -(a/3) / ln(2 x_s), so r v -> -(a r/3) / (a r/3 + ln(2a) + ln(2 pi)/3) -> -1 (slowly)
+    a = 2.0
+    r = np.array([10.0, 15.0, 20.0, 30.0])
+    rho = np.exp(-a * r) / np.pi
+    v = xc.lb94_exchange(rho, a * rho)
+    asym = -(a * r / 3) / (a * r / 3 + np.log(2 * a) + np.log(2 * np.pi) / 3)
+    np.testing.assert_allclose(v * r, asym, rtol=0.02)
+    assert np.all(np.diff(v * r) < 0) and v[-1] * r[-1] < -0.9
+    # and it is the Slater potential minus a non-negative correction
+    rho2 = np.logspace(-6, 1, 20)
+    assert np.all(xc.lb94_exchange(rho2, 0.3 * rho2) <= xc.slater_exchange(rho2) + 1e-15)
+    np.testing.assert_allclose(xc.lb94_exchange(rho2, 0 * rho2), xc.slater_exchange(rho2), rtol=1e-15)
