@@ -36,7 +36,8 @@ and H = 0.6: 36 cells per axis, 5.7 M free nodes, against 40 cells of 0.8 bohr a
 7.9 M nodes for the uniform mesh).
 
 With --frontend the set-up also times the physics front end on the target density: the
-Hartree potential by the finite-element Poisson solve and the initial guess of Eq. 25.
+Hartree potential by the finite-element Poisson solve and the initial guess of Eq. 25
+(LB94 exchange + PW92 correlation, Fermi-Amaldi tail).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0] [--vxc-h 0] [--graded 0]
                        [--frontend]
@@ -248,7 +249,7 @@ def main():
         t0 = time.perf_counter()
         v_h, pres = api.poisson_solve(mesh, rho_d, sigma=1.0, tol=1e-10)
         t1 = time.perf_counter()
-        v_init = api.xc_initial_guess(rho_d, v_h, float(wl.n_elec))
+        v_init = api.xc_initial_guess(mesh, rho_d, v_h, float(wl.n_elec), exchange="lb94")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         fe_info = {"hartree_s": t1 - t0, "hartree_cg_iters": pres.iters, "hartree_relres": pres.relres,

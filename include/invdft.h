@@ -259,14 +259,20 @@ fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma, double* p
                         int* iters_h, double* relres_h, double* charge_h, void* work, void* stream);
 
 /* ------------------------------------------------------ xc_initial_guess --
- * Eq. 25: v = f v0 + (1 - f) alpha v_FA node by node, f = rho / (rho + tau),
- * v_FA = -v_H / n_elec (Fermi-Amaldi), v0 = Slater exchange -(3 rho / pi)^{1/3}
- * + Perdew-Wang 1992 correlation of the unpolarised gas (v0 = 0 where
- * rho <= 1e-30). The paper's other choice of exchange (LB94) needs density
- * gradients and is not provided. rho, v_h, v: n device doubles. Asynchronous.
- * Errors: FE_EINVAL (NULL pointers, n < 0, n_elec <= 0, tau <= 0). */
-fe_status xc_initial_guess(const double* rho, const double* v_h, int64_t n, double n_elec, double tau,
-                           double alpha, double* v, void* stream);
+ * Eq. 25: v = f v0 + (1 - f) alpha v_FA at the free nodes, f = rho / (rho + tau),
+ * v_FA = -v_H / n_elec (Fermi-Amaldi), v0 = exchange + Perdew-Wang 1992
+ * correlation of the unpolarised gas (v0 = 0 where rho <= 1e-30). Exchange
+ * (the paper's two choices): FE_XC_SLATER, -(3 rho / pi)^{1/3}; FE_XC_LB94,
+ * Slater - beta rho_s^{1/3} x^2 / (1 + 3 beta x asinh x), rho_s = rho / 2,
+ * x = |grad rho_s| / rho_s^{4/3}, beta = 0.05, with the gradient of the order-p
+ * interpolant of the nodal density (per axis the GLL Lagrange derivative in the
+ * node's cell, the two one-sided values averaged at a shared vertex).
+ *   rho, v_h, v: N_f device doubles. work: n_cells_per_dim doubles (LB94 only,
+ *   else may be NULL). Asynchronous for Slater; synchronises the stream for LB94.
+ * Errors: FE_EINVAL (NULL pointers, n_elec <= 0, tau <= 0, unknown exchange). */
+typedef enum { FE_XC_SLATER = 0, FE_XC_LB94 = 1 } fe_xc_exchange;
+fe_status xc_initial_guess(fe_mesh mesh, const double* rho, const double* v_h, double n_elec, double tau,
+                           double alpha, int exchange, double* v, void* work, void* stream);
 
 /* ----------------------------------------------------- fermi_occupations --
  * Finite-temperature occupations (Eq. 4's Fermi-Dirac occupancy, Eq. 5):

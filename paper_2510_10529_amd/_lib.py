@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libinvdft.so")
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV, FE_ENOTPD, FE_EGAP, FE_ESTATES = range(8)
 FE_F64, FE_F32, FE_BF16 = 0, 1, 2
+FE_XC_SLATER, FE_XC_LB94 = 0, 1
 (FE_OP_KS_APPLY, FE_OP_CHEB_FILTER, FE_OP_RAYLEIGH_RITZ, FE_OP_ADJOINT_SOLVE, FE_OP_LOSS_GRAD, FE_OP_EIGENSOLVE,
  FE_OP_ALONG_PSI, FE_OP_POISSON) = range(8)
 
@@ -51,7 +52,7 @@ SIGNATURES = {
     "vxc_prolong": (C.c_int, [vp, vp, vp, vp, vp]),
     "vxc_restrict": (C.c_int, [vp, vp, vp, vp]),
     "poisson_solve": (C.c_int, [vp, vp, C.c_double, vp, C.c_double, C.c_int, ip, dp, dp, vp, vp]),
-    "xc_initial_guess": (C.c_int, [vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp]),
+    "xc_initial_guess": (C.c_int, [vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_int, vp, vp, vp]),
     "fermi_occupations": (C.c_int, [dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp,
                                     ip]),
     "adjoint_along_psi": (C.c_int, [vp, vp, C.c_int, dp, C.c_double, C.c_double, C.c_double, vp, vp, vp, dp,

@@ -326,10 +326,13 @@ def poisson_solve(mesh: Mesh, rho, sigma: float = 1.0, tol: float = 1e-12, maxit
     return phi, PoissonResult(it.value, rel.value, q.value, st)
 
 
-def xc_initial_guess(rho, v_h, n_elec: float, tau: float = 1e-2, alpha: float = 1.0, out=None):
-    """Eq. 25 with Slater exchange + PW92 correlation and the Fermi-Amaldi tail."""
+def xc_initial_guess(mesh: Mesh, rho, v_h, n_elec: float, tau: float = 1e-2, alpha: float = 1.0,
+                     exchange: str = "lb94", out=None):
+    """Eq. 25: (Slater or LB94) exchange + PW92 correlation, Fermi-Amaldi tail."""
     if out is None:
         out = torch.empty_like(rho)
-    L.check(L.load().xc_initial_guess(_ptr(rho), _ptr(v_h), rho.numel(), float(n_elec), float(tau), float(alpha),
-                                      _ptr(out), _stream()), "xc_initial_guess")
+    ex = {"slater": L.FE_XC_SLATER, "lb94": L.FE_XC_LB94}[exchange]
+    work = _work(8 * mesh.n, rho.device) if ex == L.FE_XC_LB94 else None
+    L.check(L.load().xc_initial_guess(mesh.handle, _ptr(rho), _ptr(v_h), float(n_elec), float(tau), float(alpha), ex,
+                                      _ptr(out), _ptr(work), _stream()), "xc_initial_guess")
     return out

@@ -12,8 +12,12 @@
 // potential (the same matrix-free stiffness as the Kohn-Sham operator).
 //
 // Initial guess: v = f v0 + (1 - f) alpha (-v_H / N_e), f = rho / (rho + tau),
-// v0 = Slater exchange -(3 rho / pi)^{1/3} + Perdew-Wang 1992 correlation of the
-// unpolarised gas, evaluated node by node.
+// v0 = exchange + Perdew-Wang 1992 correlation of the unpolarised gas, node by node.
+// Exchange: Slater -(3 rho / pi)^{1/3}, or van Leeuwen-Baerends (LB94), which adds
+// -beta rho_s^{1/3} x^2 / (1 + 3 beta x asinh x), x = |grad rho_s| / rho_s^{4/3},
+// rho_s = rho / 2, beta = 0.05. The gradient is that of the order-p interpolant of the
+// nodal density: per axis the GLL Lagrange derivative of the node's cell, the two
+// one-sided values averaged at a vertex shared by two cells, zero Dirichlet values.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -114,13 +118,73 @@ __device__ __forceinline__ double pw92_vc(double rho) {
   return ec - rs / 3.0 * dec;
 }
 
-__global__ void xc_init_kernel(const double* __restrict__ rho, const double* __restrict__ vh, long long n,
+struct DerivTable {
+  double d[kMaxP1 * kMaxP1];  // d[j (p+1) + k] = N_k'(xi_j) on [-1, 1]
+  int p;
+};
+
+// derivative of the interpolant along one axis at 1-D free node f (g = f + 1) of the line
+// whose free node f' sits at base + f' stride; 2/h_e per cell from inv_h2 (n entries)
+__device__ double axis_derivative(const double* __restrict__ rho, long long base, long long stride, int f, int n,
+                                  int n1, const DerivTable& D, const double* __restrict__ two_over_h) {
+  const int p = D.p;
+  const int g = f + 1;
+  const int e = g / p, j = g % p;
+  auto val = [&](int gg) { return (gg >= 1 && gg <= n1) ? rho[base + (long long)(gg - 1) * stride] : 0.0; };
+  double dr = 0.0;
+  for (int k = 0; k <= p; ++k) dr += D.d[j * (p + 1) + k] * val(e * p + k);
+  dr *= two_over_h[e];
+  if (j == 0) {  // vertex: the left cell's row p as well, averaged
+    double dl = 0.0;
+    for (int k = 0; k <= p; ++k) dl += D.d[p * (p + 1) + k] * val((e - 1) * p + k);
+    dr = 0.5 * (dr + dl * two_over_h[e - 1]);
+  }
+  return dr;
+}
+
+__global__ void xc_init_kernel(const double* __restrict__ rho, const double* __restrict__ vh, long long n, int n1,
+                               int ncell, DerivTable D, const double* __restrict__ two_over_h, int lb94,
                                double n_elec, double tau, double alpha, double* __restrict__ v) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (long long)gridDim.x * blockDim.x) {
     const double r = rho[a];
     const double f = r / (r + tau);
-    const double v0 = r > 1e-30 ? -cbrt(3.0 * r / kPi) + pw92_vc(r) : 0.0;
+    double v0 = 0.0;
+    if (r > 1e-30) {
+      v0 = -cbrt(3.0 * r / kPi) + pw92_vc(r);
+      if (lb94) {
+        int ix, iy, iz;
+        node_of(a, n1, ix, iy, iz);
+        const long long sy = n1, sz = (long long)n1 * n1;
+        const double gx = axis_derivative(rho, a - ix, 1, ix, ncell, n1, D, two_over_h);
+        const double gy = axis_derivative(rho, a - iy * sy, sy, iy, ncell, n1, D, two_over_h);
+        const double gz = axis_derivative(rho, a - iz * sz, sz, iz, ncell, n1, D, two_over_h);
+        const double rs = 0.5 * r;
+        const double x = 0.5 * sqrt(gx * gx + gy * gy + gz * gz) / (rs * cbrt(rs));
+        v0 -= 0.05 * cbrt(rs) * x * x / (1.0 + 0.15 * x * asinh(x));
+      }
+    }
     v[a] = f * v0 + (1.0 - f) * alpha * (-vh[a] / n_elec);
+  }
+}
+
+// N_k'(xi_j) at the GLL nodes from the barycentric form of the Lagrange basis
+void derivative_table(int p, DerivTable& D) {
+  std::vector<double> Kh((p + 1) * (p + 1)), Mh((p + 1) * (p + 1)), xi(p + 1), wi(p + 1);
+  reference_matrices(p, Kh.data(), Mh.data(), xi.data(), wi.data());
+  std::vector<double> bw(p + 1, 1.0);
+  for (int j = 0; j <= p; ++j)
+    for (int k = 0; k <= p; ++k)
+      if (k != j) bw[j] /= (xi[j] - xi[k]);
+  D.p = p;
+  for (int j = 0; j <= p; ++j) {
+    double diag = 0.0;
+    for (int k = 0; k <= p; ++k) {
+      if (k == j) continue;
+      const double djk = (bw[k] / bw[j]) / (xi[j] - xi[k]);
+      D.d[j * (p + 1) + k] = djk;
+      diag -= djk;
+    }
+    D.d[j * (p + 1) + j] = diag;
   }
 }
 
@@ -231,13 +295,29 @@ extern "C" fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma
   return FE_OK;
 }
 
-extern "C" fe_status xc_initial_guess(const double* rho, const double* v_h, int64_t n, double n_elec, double tau,
-                                      double alpha, double* v, void* stream) {
+extern "C" fe_status xc_initial_guess(fe_mesh mesh, const double* rho, const double* v_h, double n_elec, double tau,
+                                      double alpha, int exchange, double* v, void* work, void* stream) {
+  const Mesh* mp = mesh_tables(mesh);
+  if (!mp) return fail(FE_EINVAL, "mesh handle is NULL");
   if (!rho || !v_h || !v) return fail(FE_EINVAL, "xc_initial_guess: NULL argument");
-  if (n < 0 || !(n_elec > 0.0) || !(tau > 0.0)) return fail(FE_EINVAL, "xc_initial_guess: n >= 0, n_elec > 0, tau > 0");
-  if (n == 0) return FE_OK;
-  hipLaunchKernelGGL(xc_init_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), rho, v_h,
-                     (long long)n, n_elec, tau, alpha, v);
+  if (!(n_elec > 0.0) || !(tau > 0.0)) return fail(FE_EINVAL, "xc_initial_guess: n_elec > 0 and tau > 0 required");
+  if (exchange != FE_XC_SLATER && exchange != FE_XC_LB94) return fail(FE_EINVAL, "xc_initial_guess: unknown exchange");
+  if (exchange == FE_XC_LB94 && !work) return fail(FE_EINVAL, "xc_initial_guess: LB94 needs work");
+  const Mesh& m = *mp;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DerivTable D{};
+  double* two_over_h = static_cast<double*>(work);
+  std::vector<double> th;
+  if (exchange == FE_XC_LB94) {
+    derivative_table(m.p, D);
+    th.resize(m.n);
+    for (int e = 0; e < m.n; ++e) th[e] = 2.0 / (m.graded ? m.cell_h[e] : m.h);
+    INVDFT_HIP(hipMemcpyAsync(two_over_h, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  if (m.nf > 0)
+    hipLaunchKernelGGL(xc_init_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, rho, v_h, (long long)m.nf, m.n1, m.n, D,
+                       two_over_h, exchange == FE_XC_LB94 ? 1 : 0, n_elec, tau, alpha, v);
   INVDFT_HIP(hipGetLastError());
+  if (exchange == FE_XC_LB94) INVDFT_HIP(hipStreamSynchronize(s));   // th is read by the copy
   return FE_OK;
 }

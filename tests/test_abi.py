@@ -98,7 +98,7 @@ def test_argument_checks_without_gpu():
     assert lib.vxc_mesh_destroy(null) == _lib.FE_OK
     # physics front end
     assert lib.poisson_solve(null, None, 1.0, None, 1e-10, 10, None, None, None, None, None) == _lib.FE_EINVAL
-    assert lib.xc_initial_guess(None, None, 4, 10.0, 1e-2, 1.0, None, None) == _lib.FE_EINVAL
+    assert lib.xc_initial_guess(null, None, None, 10.0, 1e-2, 1.0, 0, None, None, None) == _lib.FE_EINVAL
     assert lib.fe_workspace_bytes(null, _lib.FE_OP_POISSON, 1, 0) == 0
 
 

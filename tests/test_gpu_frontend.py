@@ -5,7 +5,8 @@ finite-element Poisson solve and the initial guess of Eq. 25, against the oracle
   (p >= 3) is reproduced by the conjugate-gradient solve;
 * two Gaussian charges on the ho-q2-12 mesh, with the monopole split off, against the
   oracle's direct sparse solve of the same discrete problem;
-* the initial guess node by node against the oracle's formulas, from empty to dense;
+* the initial guess node by node against the oracle's formulas, from empty to dense, with
+  Slater and with LB94 exchange (through the nodal gradient, on uniform and graded cells);
 * at full size, the target density of mol100-q5-40 (7,880,599 nodes): the charge, the
   solver's residual, the discrete equation on sampled rows evaluated one by one from the
   oracle's Kronecker rows and the closed-form Gaussian, and the far field ~ Q / r.
@@ -62,15 +63,28 @@ def test_poisson_gaussian_charges_against_oracle():
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
-def test_initial_guess_against_oracle():
+@pytest.mark.parametrize("graded", [False, True])
+def test_initial_guess_against_oracle(graded):
+    """Slater and LB94 on a density with empty, tiny and dense nodes; LB94 through the nodal
+    gradient of the order-p interpolant (uniform and graded cells)."""
     from paper_2510_10529_amd import api
+    from synth import vxc_vertices
+    if graded:
+        t = vxc_vertices(8.0, 1.0, 3.0, 1.6)
+        m, om = api.Mesh(3, 0, 0.0, breaks=t), fe.mesh3d_graded(3, t)
+    else:
+        m, om = api.Mesh(3, 8, 8.0), fe.mesh3d(3, 8, 8.0)
+    X = om.coords()
     rng = np.random.default_rng(12)
-    rho = np.concatenate([[0.0, 1e-40, 1e-12, 1e-6], 10 ** rng.uniform(-8, 2, 2000)])
-    vh = rng.uniform(0.0, 20.0, rho.size)
-    for tau, alpha in ((1e-2, 1.0), (1e-3, 0.25)):
-        got = api.xc_initial_guess(_t(rho), _t(vh), 100.0, tau=tau, alpha=alpha).cpu().numpy()
-        ref = xc.initial_guess(rho, vh, 100.0, tau=tau, alpha=alpha)
-        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+    rho = 5.0 * np.exp(-0.5 * np.sum((X - 0.3) ** 2, axis=1)) + 0.5 * np.exp(-2 * np.sum((X + 1) ** 2, axis=1))
+    rho[rng.integers(0, om.n_free, 50)] = 0.0
+    vh = rng.uniform(0.0, 20.0, om.n_free)
+    grad = np.linalg.norm(fe.nodal_gradient(om, rho), axis=1)
+    for ex, gn in (("slater", None), ("lb94", grad)):
+        for tau, alpha in ((1e-2, 1.0), (1e-3, 0.25)):
+            got = api.xc_initial_guess(m, _t(rho), _t(vh), 100.0, tau=tau, alpha=alpha, exchange=ex).cpu().numpy()
+            ref = xc.initial_guess(rho, vh, 100.0, tau=tau, alpha=alpha, grad_norm=gn)
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-13)
 
 
 def test_hartree_full_size():
@@ -109,6 +123,8 @@ def test_hartree_full_size():
     ratio = ph[far] * np.linalg.norm(X[far] - c, axis=1) / Q
     _say(f"far field: phi |r - c| / Q in [{ratio.min():.4f}, {ratio.max():.4f}]")
     assert ratio.min() > 0.97 and ratio.max() < 1.03
-    vi = api.xc_initial_guess(rho, phi, float(wl.n_elec)).cpu().numpy()
+    vi = api.xc_initial_guess(m, rho, phi, float(wl.n_elec), exchange="lb94").cpu().numpy()
+    gn = np.linalg.norm(fe.nodal_gradient(om, rh), axis=1)
     sel = rows
-    np.testing.assert_allclose(vi[sel], xc.initial_guess(rh[sel], ph[sel], float(wl.n_elec)), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(vi[sel], xc.initial_guess(rh[sel], ph[sel], float(wl.n_elec), grad_norm=gn[sel]),
+                               rtol=1e-10, atol=1e-13)
