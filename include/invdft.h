@@ -35,10 +35,12 @@
  * concurrently.
  *
  * Precision: FE_F64 -> double blocks and FP64 arithmetic. FE_F32 -> float
- * blocks, FP32 arithmetic. FE_BF16 is accepted where stated: float blocks, the
- * kinetic contraction rounded to bfloat16 (round to nearest even) with FP32
- * accumulation. Potentials, weights, densities, Gram matrices, eigenvalues and
- * every reduction are always FP64.
+ * blocks, FP32 arithmetic. FE_BF16 is reserved: every operation returns
+ * FE_EINVAL for it (a bfloat16 contraction was considered for the filter and
+ * not built: its 8-bit mantissa sits above the residual level the warm-started
+ * filter works at, and the sum-factorised apply has no matrix-core shape).
+ * Potentials, weights, densities, Gram matrices, eigenvalues and every
+ * reduction are always FP64.
  *
  * Errors: a non-zero fe_status never aborts the process; fe_last_error()
  * returns a thread-local message describing the last failure of this thread.
@@ -133,7 +135,7 @@ const char* fe_last_error(void);
  *   v: N_f doubles (always FP64). shift_h: nv host doubles or NULL (no shift),
  *   at most 256 columns when given. X, Y: N_f x ld blocks of the precision's
  *   type; Y must not alias X.
- * prec: FE_F64, FE_F32 or FE_BF16. */
+ * prec: FE_F64 or FE_F32 (FE_EINVAL otherwise). */
 fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const void* X, void* Y,
                    int nv, int ld, fe_prec prec, void* stream);
 
@@ -143,7 +145,7 @@ fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const v
  *   p_m(lambda) = T_m((lambda - c)/e) / T_m((a0 - c)/e),
  * which damps [a, b] and keeps the columns O(1) near a0 < a.
  *   degree >= 1, a < b, a0 < a. work: fe_workspace_bytes(FE_OP_CHEB_FILTER).
- * prec: FE_F64, FE_F32 or FE_BF16 (X's type follows prec). */
+ * prec: FE_F64 or FE_F32 (X's type follows prec; FE_EINVAL otherwise). */
 fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, double b, double a0,
                       void* X, int nv, int ld, fe_prec prec, void* work, void* stream);
 
@@ -163,7 +165,7 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
  * block X (nv > nocc; start from a random or warm block) until
  * max_{i < nocc} ||H~ x_i - eig_i x_i|| <= tol or maxpass passes. The filter
  * bounds are b = kinetic bound + max(v), a = largest Ritz value, a0 = smallest.
- * prec selects the filter precision (FE_F64 / FE_F32 / FE_BF16); with a
+ * prec selects the filter precision (FE_F64 / FE_F32; FE_EINVAL otherwise); with a
  * reduced precision the passes switch to FP64 once the residual is below
  * `switch_tol`, so the final accuracy is FP64's. Rayleigh-Ritz is FP64.
  *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.

@@ -228,3 +228,15 @@ def test_adjoint_noconv_status():
     Q, ar = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-14, maxit=1)
     assert ar.status == _lib.FE_ENOCONV
     assert all(i == 1 for i in ar.iters)
+
+
+def test_bf16_is_rejected():
+    """FE_BF16 is reserved: the operators refuse it before any device work."""
+    from paper_2510_10529_amd import _lib
+    api = _api()
+    m, om = _mesh_pair(2, 6, 4.0)
+    X = torch.zeros((om.n_free, 4), dtype=torch.float32, device=DEV)
+    v = torch.zeros(om.n_free, dtype=torch.float64, device=DEV)
+    with pytest.raises(_lib.FEError) as e:
+        api.ks_apply(m, v, X, prec="bf16")
+    assert e.value.status == _lib.FE_EINVAL
