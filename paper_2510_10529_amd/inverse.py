@@ -89,9 +89,12 @@ class InverseProblem:
             if not 0 < self.nconv < self.nv:
                 raise ValueError("finite temperature needs 0 < n_states < block width")
         else:
-            self.nconv = n_elec // 2
+            if n_elec != int(n_elec):
+                raise ValueError("zero temperature needs an integer electron count")
+            self.nconv = int(n_elec) // 2
         self.nocc = self.nconv                 # widest block of orbitals that can enter
-        self.state = OccState(n_elec // 2, [2.0] * (n_elec // 2), [])
+        n0 = int(n_elec) // 2                  # placeholder until the first eigensolve
+        self.state = OccState(n0, [2.0] * n0, [])
         self.X = X0.clone()                    # FP64 warm-start block (Ritz vectors)
         self.v = torch.empty_like(v_fixed)
         self.eig = None
