@@ -82,7 +82,8 @@ typedef enum {
   FE_OP_LOSS_GRAD = 4,
   FE_OP_EIGENSOLVE = 5,
   FE_OP_ALONG_PSI = 6,
-  FE_OP_POISSON = 7
+  FE_OP_POISSON = 7,
+  FE_OP_ADJOINT_DEFLATED = 8
 } fe_op;
 
 /* ------------------------------------------------------------------ mesh --
@@ -122,7 +123,8 @@ fe_status fe_mesh_destroy(fe_mesh mesh);
 
 /* Bytes of device work buffer an operation needs for a block of nv columns
  * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD, nv = n for
- * FE_OP_ALONG_PSI, nv = 1 for FE_OP_POISSON). 0 on bad input. */
+ * FE_OP_ALONG_PSI, nv = 1 for FE_OP_POISSON, nv = nocc + nbuf for
+ * FE_OP_ADJOINT_DEFLATED, FP64 only). 0 on bad input. */
 size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec);
 
 const char* fe_last_error(void);
@@ -197,6 +199,34 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
 fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h,
                         int nocc, const double* B, double* Q, double tol, int maxit, int* iters_h,
                         double* relres_h, fe_prec prec, void* work, void* stream);
+
+/* ------------------------------------------------ adjoint_solve_deflated --
+ * The same solve as adjoint_solve in FP64 (same system, Eq. 20 of Sec. 3.2.2,
+ * same solution up to tol), with a preconditioner that also inverts the shifted
+ * operator on nbuf further approximate eigenvectors U whose Rayleigh quotients
+ * theta lie above every shift:
+ *   M_i = P_V D^{-1} P_V + U diag(1 / (theta_j - eps_i)) U^T,  P_V = I - V V^T,
+ *   V = [Psi U], D = diag(K~_aa/2).
+ * M_i is symmetric positive definite on the complement of Psi for any U, so the
+ * solution does not depend on U; only the iteration count does. The columns
+ * whose shift lies closest to the rest of the spectrum (smallest gap) gain
+ * the most. The paper's solver uses the plain diagonal preconditioner; this is
+ * an addition on the same path, not a change of the method.
+ *   U: N_f x nbuf (ld = nbuf), orthonormal columns orthogonal to Psi, e.g. the
+ *   Ritz vectors of the eigensolve above the occupied ones (a copy of U with
+ *   Psi projected out is used, the caller's U is not modified);
+ *   theta_h: nbuf host doubles, each strictly greater than every eps_h[i].
+ * Other arguments as adjoint_solve. 1 <= nocc, 1 <= nbuf, nocc + nbuf <= 64.
+ * FE_EINVAL on bad sizes, NULL or unaligned pointers, or theta not above every
+ * shift; FE_ENOCONV when some column did not reach tol in maxit iterations
+ * (Q, iters_h and relres_h are filled all the same).
+ * work: fe_workspace_bytes(FE_OP_ADJOINT_DEFLATED, nocc + nbuf, FE_F64).
+ * Synchronises the stream. */
+fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Psi,
+                                 const double* eps_h, int nocc, const double* U,
+                                 const double* theta_h, int nbuf, const double* B, double* Q,
+                                 double tol, int maxit, int* iters_h, double* relres_h,
+                                 void* work, void* stream);
 
 /* ------------------------------------------------------------- loss_grad --
  * Phase 1 (Q == NULL): rho_a = sum_i f_i psi_{a,i}^2 / W_a (Eq. 4),

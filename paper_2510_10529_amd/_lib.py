@@ -14,7 +14,7 @@ FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV, FE_ENOTPD, FE_EGAP, FE_ESTA
 FE_F64, FE_F32, FE_BF16 = 0, 1, 2
 FE_XC_SLATER, FE_XC_LB94 = 0, 1
 (FE_OP_KS_APPLY, FE_OP_CHEB_FILTER, FE_OP_RAYLEIGH_RITZ, FE_OP_ADJOINT_SOLVE, FE_OP_LOSS_GRAD, FE_OP_EIGENSOLVE,
- FE_OP_ALONG_PSI, FE_OP_POISSON) = range(8)
+ FE_OP_ALONG_PSI, FE_OP_POISSON, FE_OP_ADJOINT_DEFLATED) = range(9)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE", 4: "FE_ENOCONV",
                 5: "FE_ENOTPD", 6: "FE_EGAP", 7: "FE_ESTATES"}
@@ -41,6 +41,8 @@ SIGNATURES = {
     "ks_eigensolve": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                 C.c_double, dp, dp, ip, vp, vp]),
     "adjoint_solve": (C.c_int, [vp, vp, vp, dp, C.c_int, vp, vp, C.c_double, C.c_int, ip, dp, C.c_int, vp, vp]),
+    "adjoint_solve_deflated": (C.c_int, [vp, vp, vp, dp, C.c_int, vp, dp, C.c_int, vp, vp, C.c_double, C.c_int, ip,
+                                         dp, vp, vp]),
     "loss_grad": (C.c_int, [vp, vp, dp, C.c_int, vp, vp, C.c_double, vp, vp, vp, dp, vp, vp]),
     "fe_dot": (C.c_int, [vp, vp, C.c_int64, dp, vp, vp]),
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),

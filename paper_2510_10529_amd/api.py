@@ -206,14 +206,27 @@ class AdjResult:
 
 
 def adjoint_solve(mesh: Mesh, v, Psi, eps, B, Q=None, tol: float = 1e-10, maxit: int = 5000, prec: str = "f64",
-                  work=None, allow=(L.FE_ENOCONV,)) -> tuple:
+                  work=None, allow=(L.FE_ENOCONV,), U=None, theta=None) -> tuple:
+    """MINRES adjoint solve; with U (N_f x nbuf) and theta (nbuf values above every shift)
+    the deflated preconditioner of ``adjoint_solve_deflated`` is used (FP64 only)."""
     k = Psi.shape[1]
     if Q is None:
         Q = torch.empty_like(B)
-    if work is None:
-        work = _work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, k, prec), Psi.device)
     its = (C.c_int * k)()
     rel = (C.c_double * k)()
+    if U is not None:
+        if prec != "f64":
+            raise ValueError("the deflated adjoint solve is FP64 only")
+        nb = U.shape[1]
+        if work is None:
+            work = _work(mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED, k + nb, "f64"), Psi.device)
+        st = L.load().adjoint_solve_deflated(mesh.handle, _ptr(v), _ptr(Psi), _host_doubles(eps), k, _ptr(U),
+                                             _host_doubles(theta), nb, _ptr(B), _ptr(Q), float(tol), int(maxit), its,
+                                             rel, _ptr(work), _stream())
+        L.check(st, "adjoint_solve_deflated", allow=allow)
+        return Q, AdjResult(list(its), list(rel), st)
+    if work is None:
+        work = _work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, k, prec), Psi.device)
     st = L.load().adjoint_solve(mesh.handle, _ptr(v), _ptr(Psi), _host_doubles(eps), k, _ptr(B), _ptr(Q),
                                 float(tol), int(maxit), its, rel, PREC[prec], _ptr(work), _stream())
     L.check(st, "adjoint_solve", allow=allow)

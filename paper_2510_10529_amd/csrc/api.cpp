@@ -284,10 +284,46 @@ fe_status fill_t<float>(float* y, int64_t n, hipStream_t s) { return fill_f32(y,
 // once enough of them have: the solve's cost then follows the still-active columns.
 // On return `iters` holds per-column iteration counts, `active` the still-unconverged flags
 // (both in the original column order).
+// Deflation of the preconditioner (FP64 only): with U (N x nb, orthonormal, orthogonal to
+// Psi) approximate eigenvectors above every shift, Rayleigh quotients theta,
+//   M = P_ext D^{-1} P_ext + U diag(1 / (theta - eps_i)) U^T,   P_ext = I - V V^T, V = [Psi U].
+// M is symmetric positive definite on the complement of Psi whatever the quality of U, so
+// the solution is unchanged; the Krylov space no longer has to resolve the low states U
+// captures, which are what slows the columns with the smallest gaps. The stored Lanczos
+// vectors are r' = r - U c with c = U^T r kept as small per-column arrays; the fused passes
+// then run with V in place of Psi (pass B's subtraction V (V^T y) is exactly the deflated
+// recurrence), plus four small per-column corrections.
+struct Deflation {
+  const double* V;      // [Psi U], N x (k0 + nb)
+  const double* U;      // N x nb
+  int nb;
+  const double* theta;  // nb (device)
+  double* eps;          // shifts of the current columns (device, k)
+  double *cA, *cB, *cC, *tmp;  // nb x k small arrays (device)
+};
+
+// Extra work of a deflated solve with nocc shifts and nb deflation vectors; pw replaces
+// MRWork's projection scratch (V is wider than Psi).
+Deflation defl_layout(Bump& bp, const Mesh& m, int k, int nb, double** Ucopy, double** pw) {
+  Deflation d{};
+  *Ucopy = bp.take<double>((size_t)m.nf * nb);
+  d.V = bp.take<double>((size_t)m.nf * (k + nb));
+  d.U = *Ucopy;
+  d.nb = nb;
+  d.theta = bp.take<double>(64);
+  d.eps = bp.take<double>(64);
+  d.cA = bp.take<double>(64 * 64);
+  d.cB = bp.take<double>(64 * 64);
+  d.cC = bp.take<double>(64 * 64);
+  d.tmp = bp.take<double>(64 * 64);
+  *pw = bp.take<double>(project_work_bytes(m.nf, 64, 64) / sizeof(double) + 1);
+  return d;
+}
+
 template <typename T>
 fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double* eps_h, int k0, const T* B, T* Q,
                       double tol, int maxit, MRWork& w, std::vector<double>& iters, std::vector<double>& active,
-                      hipStream_t s) {
+                      hipStream_t s, Deflation* df = nullptr) {
   const int64_t nf = m.nf;
   const bool f32 = sizeof(T) == sizeof(float);
   const fe_prec prec = f32 ? FE_F32 : FE_F64;
@@ -300,12 +336,39 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
   if ((st = fill_t<T>(Qw, blk, s)) != FE_OK) return st;
   if ((st = fill_t<T>(Wa, blk, s)) != FE_OK) return st;
   if ((st = fill_t<T>(Wb, blk, s)) != FE_OK) return st;
-  if ((st = copy_bytes(B, R1, blk * sizeof(T), s)) != FE_OK) return st;
-  if ((st = copy_bytes(B, R2, blk * sizeof(T), s)) != FE_OK) return st;
-  // z = P D^{-1} b ; beta1 = sqrt(b.z)
-  if ((st = k_precond<T>(B, w.dinv, k, nf, Z, s)) != FE_OK) return st;
-  if ((st = project_out(Psi, k0, Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
-  if ((st = coldot(R1, Z, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
+  const bool defl = df != nullptr;
+  const T* Pj = Psi;     // the block the fused passes project with
+  int kp = k0;
+  double *cR1 = nullptr, *cR2 = nullptr, *cN = nullptr;
+  if (!defl) {
+    if ((st = copy_bytes(B, R1, blk * sizeof(T), s)) != FE_OK) return st;
+    if ((st = copy_bytes(B, R2, blk * sizeof(T), s)) != FE_OK) return st;
+    // z = P D^{-1} b ; beta1 = sqrt(b.z)
+    if ((st = k_precond<T>(B, w.dinv, k, nf, Z, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, k0, Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
+  } else {
+    if constexpr (sizeof(T) == sizeof(double)) {
+      Pj = df->V;
+      kp = k0 + df->nb;
+      cR1 = df->cA;
+      cR2 = df->cB;
+      cN = df->cC;
+      const int nb = df->nb;
+      // c0 = U^T b ; r' = b - U c0 (R1 and R2) ; z = P_ext D^{-1} r' + U c0 / (theta - eps) ; beta1^2 = b.z
+      if ((st = gram(df->U, nb, B, k, nf, nb, k, false, cR1, w.pw, s)) != FE_OK) return st;
+      if ((st = copy_bytes(cR1, cR2, (size_t)nb * k * sizeof(double), s)) != FE_OK) return st;
+      if ((st = copy_bytes(B, R1, blk * sizeof(T), s)) != FE_OK) return st;
+      if ((st = rotate_axpy(df->U, nb, nf, nb, cR1, k, -1.0, R1, k, s)) != FE_OK) return st;
+      if ((st = copy_bytes(R1, R2, blk * sizeof(T), s)) != FE_OK) return st;
+      if ((st = k_precond<T>(R1, w.dinv, k, nf, Z, s)) != FE_OK) return st;
+      if ((st = project_out(Pj, kp, Z, k, nf, false, w.pw, s)) != FE_OK) return st;
+      if ((st = defl_scale(cR1, df->theta, df->eps, k, nb, df->tmp, s)) != FE_OK) return st;
+      if ((st = rotate_axpy(df->U, nb, nf, nb, df->tmp, k, 1.0, Z, k, s)) != FE_OK) return st;
+    } else {
+      return fail(FE_EINVAL, "adjoint_solve: deflation needs FP64");
+    }
+  }
+  if ((st = coldot(B, Z, k, nf, k, f32, w.d1, w.pw, s)) != FE_OK) return st;
   if ((st = mr_init(w.st, w.d1, k, s)) != FE_OK) return st;
   std::vector<int> orig(k0);
   for (int j = 0; j < k0; ++j) orig[j] = j;
@@ -342,14 +405,23 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
     aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
     if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
     // one sweep: G = Psi^T y, z.y, z.r1; alfa = v.(P y - c1 r1) = v.y - c1 v.r1 (v is orthogonal to Psi)
-    if ((st = minres_pass_a<T>(Psi, k0, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
+    if ((st = minres_pass_a<T>(Pj, kp, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
+    if (defl && (st = defl_d2(fw.d2, cR1, cR2, df->theta, df->eps, k, df->nb, s)) != FE_OK) return st;
     if ((st = mr_alfa(w.st, fw.d1, fw.d2, k, it == 1, s)) != FE_OK) return st;
+    if (defl && (st = defl_cnew(fw.G, k0, df->nb, cR1, cR2, w.st, k, cN, s)) != FE_OK) return st;
     // r_new = P y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; G2 = Psi^T u ; beta^2 = r_new.u
-    if ((st = minres_pass_b<T>(Psi, k0, Y, R1, R2, w.st, w.dinv, k, nf, fw, s)) != FE_OK) return st;
+    if ((st = minres_pass_b<T>(Pj, kp, Y, R1, R2, w.st, w.dinv, k, nf, fw, s)) != FE_OK) return st;
+    if (defl) {
+      if ((st = defl_beta_g2(fw.d, fw.G2, k0, df->nb, cN, df->theta, df->eps, k, s)) != FE_OK) return st;
+      double* t = cR1;  // the coefficients follow the vectors: cR1 <- cR2, cR2 <- c_new
+      cR1 = cR2;
+      cR2 = cN;
+      cN = t;
+    }
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
     if ((st = mr_givens(w.st, fw.d, k, tol, s)) != FE_OK) return st;
     // z_new = P u (into Y) ; w and q updates with the new rotation
-    if ((st = minres_pass_c<T>(Psi, k0, Y, Z, Wb, Wa, Qw, w.st, k, nf, fw, s)) != FE_OK) return st;
+    if ((st = minres_pass_c<T>(Pj, kp, Y, Z, Wb, Wa, Qw, w.st, k, nf, fw, s)) != FE_OK) return st;
     std::swap(Wa, Wb);
     std::swap(Z, Y);  // Y now holds the previous z: free until the next apply
     if (it % check_every == 0 || it == maxit) {
@@ -382,6 +454,20 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
         }
         orig.swap(orig2);
         eps.swap(eps2);
+        if (defl) {
+          // compact the small coefficient arrays and the device shifts the same way
+          const int nb = df->nb;
+          std::vector<double> ch((size_t)nb * k), cc((size_t)nb * na);
+          for (double* c : {cR1, cR2}) {
+            INVDFT_HIP(hipMemcpyAsync(ch.data(), c, ch.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            INVDFT_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < nb; ++j)
+              for (int i = 0; i < na; ++i) cc[(size_t)j * na + i] = ch[(size_t)j * k + keep[i]];
+            INVDFT_HIP(hipMemcpyAsync(c, cc.data(), cc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            INVDFT_HIP(hipStreamSynchronize(s));
+          }
+          INVDFT_HIP(hipMemcpyAsync(df->eps, eps.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        }
         k = na;
         INVDFT_HIP(hipStreamSynchronize(s));  // host vectors above are sources of async copies
       }
@@ -651,6 +737,13 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
     case FE_OP_RAYLEIGH_RITZ: rr_layout(bp, m, nv, nv); return bp.off;
     case FE_OP_EIGENSOLVE: eig_layout(bp, m, nv, nv, prec); return bp.off;
     case FE_OP_ADJOINT_SOLVE: mr_layout(bp, m, nv, prec); return bp.off;
+    case FE_OP_ADJOINT_DEFLATED: {  // nv = nocc + nbuf: a bound for every split of nv
+      if (nv > 64) return 0;
+      double *u, *pw;
+      mr_layout(bp, m, nv, FE_F64);
+      defl_layout(bp, m, nv, nv, &u, &pw);
+      return bp.off;
+    }
     case FE_OP_LOSS_GRAD:
       bp.take<double>(m.nf);
       bp.take<double>(1025);
@@ -804,6 +897,67 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
   return FE_OK;
 }
 
+// The FP64 solve and its true residual; reports per-column counts and relative residuals.
+fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k, const double* B,
+                      double* Q, double tol, int maxit, int* iters_h, double* relres_h, MRWork& w, Deflation* df,
+                      const char* name, hipStream_t s) {
+  fe_status st;
+  std::vector<double> its, active, rr(k), bb(k);
+  bool conv = true;
+  if ((st = minres_core<double>(m, v, Psi, eps_h, k, B, Q, tol, maxit, w, its, active, s, df)) != FE_OK) return st;
+  for (int j = 0; j < k; ++j)
+    if (active[j] > 0.0) conv = false;
+  if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, static_cast<double*>(w.Y), w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  INVDFT_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    if (iters_h) iters_h[j] = (int)its[j];
+    if (relres_h) relres_h[j] = bb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / bb[j]) : 0.0;
+  }
+  if (!conv) {
+    std::string msg = std::string(name) + ": some columns did not converge in maxit iterations";
+    return fail(FE_ENOCONV, msg.c_str());
+  }
+  return FE_OK;
+}
+
+fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h, int nocc,
+                                 const double* U, const double* theta_h, int nbuf, const double* B, double* Q,
+                                 double tol, int maxit, int* iters_h, double* relres_h, void* work, void* stream) {
+  if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
+  if (!v || !Psi || !eps_h || !U || !theta_h || !B || !Q || !work)
+    return fail(FE_EINVAL, "adjoint_solve_deflated: NULL argument");
+  if (!aligned16(Psi) || !aligned16(U) || !aligned16(B) || !aligned16(Q) || !aligned16(work))
+    return fail(FE_EINVAL, "adjoint_solve_deflated: Psi, U, B, Q and work must be 16-byte aligned");
+  if (nocc < 1 || nbuf < 1 || nocc + nbuf > 64)
+    return fail(FE_EINVAL, "adjoint_solve_deflated: nocc >= 1, nbuf >= 1 and nocc + nbuf <= 64 required");
+  if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve_deflated: tol > 0 and maxit >= 1 required");
+  double emax = eps_h[0], tmin = theta_h[0];
+  for (int i = 0; i < nocc; ++i) emax = std::max(emax, eps_h[i]);
+  for (int j = 0; j < nbuf; ++j) tmin = std::min(tmin, theta_h[j]);
+  if (!(tmin > emax) || !std::isfinite(tmin) || !std::isfinite(emax))
+    return fail(FE_EINVAL, "adjoint_solve_deflated: every theta must lie above every shift");
+  const Mesh& m = mesh->m;
+  hipStream_t s = S(stream);
+  Bump bp(work);
+  MRWork w = mr_layout(bp, m, nocc, FE_F64);
+  double *Uc, *pw;
+  Deflation df = defl_layout(bp, m, nocc, nbuf, &Uc, &pw);
+  w.pw = pw;
+  fe_status st;
+  if ((st = k_dinv(m, w.dinv, s)) != FE_OK) return st;
+  // U with Psi projected out (twice: the Ritz vectors are orthogonal to Psi only to rounding)
+  if ((st = copy_bytes(U, Uc, (size_t)m.nf * nbuf * sizeof(double), s)) != FE_OK) return st;
+  for (int pass = 0; pass < 2; ++pass)
+    if ((st = project_out(Psi, nocc, Uc, nbuf, m.nf, false, w.pw, s)) != FE_OK) return st;
+  if ((st = defl_pack(Psi, nocc, Uc, nbuf, const_cast<double*>(df.V), m.nf, s)) != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(const_cast<double*>(df.theta), theta_h, nbuf * sizeof(double), hipMemcpyHostToDevice, s));
+  INVDFT_HIP(hipMemcpyAsync(df.eps, eps_h, nocc * sizeof(double), hipMemcpyHostToDevice, s));
+  return adjoint_f64(m, v, Psi, eps_h, nocc, B, Q, tol, maxit, iters_h, relres_h, w, &df, "adjoint_solve_deflated", s);
+}
+
 fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h, int nocc,
                         const double* B, double* Q, double tol, int maxit, int* iters_h, double* relres_h, fe_prec prec,
                         void* work, void* stream) {
@@ -825,11 +979,7 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
   std::vector<double> its, active, total_its(k, 0.0), rr(k), bb(k);
   bool conv = true;
   if (prec == FE_F64) {
-    if ((st = minres_core<double>(m, v, Psi, eps_h, k, B, Q, tol, maxit, w, its, active, s)) != FE_OK) return st;
-    total_its = its;
-    for (int j = 0; j < k; ++j)
-      if (active[j] > 0.0) conv = false;
-    if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, static_cast<double*>(w.Y), w.d1, w.pw, s)) != FE_OK) return st;
+    return adjoint_f64(m, v, Psi, eps_h, k, B, Q, tol, maxit, iters_h, relres_h, w, nullptr, "adjoint_solve", s);
   } else {
     // FP32 MINRES inner solves with FP64 iterative refinement: q += d, (H - eps) d = r in FP32,
     // r = b - (H - eps) q in FP64, until every column reaches tol.
@@ -881,7 +1031,6 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
     }
     if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
   }
-  if (prec == FE_F64 && (st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipStreamSynchronize(s));

@@ -361,11 +361,16 @@ fe_status gram_weighted(const double* X, int ld, const double* wa, const double*
 
 fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* Y, int ldy,
                      hipStream_t s) {
+  return rotate_axpy(X, ldx, N, nin, C, nout, 1.0, Y, ldy, s);
+}
+
+fe_status rotate_axpy(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double alpha, double* Y,
+                      int ldy, hipStream_t s) {
   if (nin > 64 || nout > 64) return fail(FE_EINVAL, "rotate: blocks wider than 64 columns are not supported");
   if (N <= 0) return FE_OK;
   const unsigned grid = (unsigned)((N + 63) / 64);
-  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, 1.0, 1.0,
-                     (const double*)Y, Y, ldy);
+  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, alpha,
+                     1.0, (const double*)Y, Y, ldy);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

@@ -98,6 +98,9 @@ size_t poisson_work_bytes(int64_t nf);
 // Y += X C over N rows (X: N x nin, C: nin x nout row-major on the device, Y: N x nout).
 fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* Y, int ldy,
                      hipStream_t s);
+// Y += alpha X C
+fe_status rotate_axpy(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double alpha, double* Y,
+                      int ldy, hipStream_t s);
 size_t coldot_work_bytes(int64_t N, int nv);
 fe_status coldot(const void* X, const void* Y, int ld, int64_t N, int nv, bool f32, double* out, void* work,
                  hipStream_t s);

@@ -212,6 +212,69 @@ __global__ void mr_givens_kernel(double* __restrict__ st, const double* __restri
 
 
 
+// ------------------------------------------------- deflated preconditioner
+// M = P_ext D^{-1} P_ext + U diag(1 / (theta - eps_i)) U^T with V = [Psi U] orthonormal,
+// P_ext = I - V V^T; the stored Lanczos vectors are r' = r - U c, c = U^T r (nb x k small
+// arrays c[j k + i]); G blocks from the fused passes are (k0 + nb) x k row-major.
+
+// V[a, 0..k0) = Psi[a, :], V[a, k0..k0+nb) = U[a, :]
+__global__ void defl_pack_kernel(const double* __restrict__ Psi, int k0, const double* __restrict__ U, int nb,
+                                 double* __restrict__ V, long long nf) {
+  const int kp = k0 + nb;
+  const long long total = nf * kp;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long a = e / kp;
+    const int c = (int)(e % kp);
+    V[e] = c < k0 ? Psi[a * k0 + c] : U[a * nb + (c - k0)];
+  }
+}
+
+// d2_i += sum_j cR1[j, i] cR2[j, i] / (theta_j - eps_i): z.r1 with r1 = r1' + U cR1 and U^T z = cR2 / (theta - eps)
+__global__ void defl_d2_kernel(double* __restrict__ d2, const double* __restrict__ cR1, const double* __restrict__ cR2,
+                               const double* __restrict__ theta, const double* __restrict__ eps, int k, int nb) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double t = 0.0;
+    for (int j = 0; j < nb; ++j) t += cR1[j * k + i] * cR2[j * k + i] / (theta[j] - eps[i]);
+    d2[i] += t;
+  }
+}
+
+// c_new = U^T y - c1 cR1 - c2 cR2 (U^T y: rows k0.. of G1 from pass A)
+__global__ void defl_cnew_kernel(const double* __restrict__ G1, int k0, int nb, const double* __restrict__ cR1,
+                                 const double* __restrict__ cR2, const double* __restrict__ st, int k,
+                                 double* __restrict__ cnew) {
+  for (int e = threadIdx.x; e < nb * k; e += blockDim.x) {
+    const int j = e / k, i = e % k;
+    cnew[e] = G1[(k0 + j) * k + i] - st[S_C1 * k + i] * cR1[e] - st[S_C2 * k + i] * cR2[e];
+  }
+}
+
+// beta^2 = r'.D^{-1} r' + sum_j c_new^2 / (theta_j - eps_i); the U rows of G2 lose c_new / (theta - eps)
+// so that pass C forms z = P_ext D^{-1} r' + U c_new / (theta - eps)
+__global__ void defl_beta_g2_kernel(double* __restrict__ d, double* __restrict__ G2, int k0, int nb,
+                                    const double* __restrict__ cnew, const double* __restrict__ theta,
+                                    const double* __restrict__ eps, int k) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double t = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const double c = cnew[j * k + i];
+      const double g = 1.0 / (theta[j] - eps[i]);
+      t += c * c * g;
+      G2[(k0 + j) * k + i] -= c * g;
+    }
+    d[i] += t;
+  }
+}
+
+// out[j, i] = c[j, i] / (theta_j - eps_i)
+__global__ void defl_scale_kernel(const double* __restrict__ c, const double* __restrict__ theta,
+                                  const double* __restrict__ eps, int k, int nb, double* __restrict__ out) {
+  for (int e = threadIdx.x; e < nb * k; e += blockDim.x) {
+    const int j = e / k, i = e % k;
+    out[e] = c[e] / (theta[j] - eps[i]);
+  }
+}
+
 __global__ void dinv_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
                             double* __restrict__ dinv) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
@@ -340,6 +403,41 @@ int mr_state_count() { return S_COUNT; }
 int mr_state_iters() { return S_ITERS; }
 int mr_state_active() { return S_ACTIVE; }
 int mr_state_invbeta() { return S_INVBETA; }
+
+fe_status defl_pack(const double* Psi, int k0, const double* U, int nb, double* V, int64_t nf, hipStream_t s) {
+  hipLaunchKernelGGL(defl_pack_kernel, dim3(grid_for(nf * (k0 + nb))), dim3(256), 0, s, Psi, k0, U, nb, V,
+                     (long long)nf);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status defl_d2(double* d2, const double* cR1, const double* cR2, const double* theta, const double* eps, int k,
+                  int nb, hipStream_t s) {
+  hipLaunchKernelGGL(defl_d2_kernel, dim3(1), dim3(64), 0, s, d2, cR1, cR2, theta, eps, k, nb);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status defl_cnew(const double* G1, int k0, int nb, const double* cR1, const double* cR2, const double* st, int k,
+                    double* cnew, hipStream_t s) {
+  hipLaunchKernelGGL(defl_cnew_kernel, dim3(1), dim3(256), 0, s, G1, k0, nb, cR1, cR2, st, k, cnew);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status defl_beta_g2(double* d, double* G2, int k0, int nb, const double* cnew, const double* theta,
+                       const double* eps, int k, hipStream_t s) {
+  hipLaunchKernelGGL(defl_beta_g2_kernel, dim3(1), dim3(64), 0, s, d, G2, k0, nb, cnew, theta, eps, k);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status defl_scale(const double* c, const double* theta, const double* eps, int k, int nb, double* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(defl_scale_kernel, dim3(1), dim3(256), 0, s, c, theta, eps, k, nb, out);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
 
 fe_status mr_init(double* st, const double* dot_r_z, int k, hipStream_t s) {
   hipLaunchKernelGGL(mr_init_kernel<double>, dim3(1), dim3(256), 0, s, st, dot_r_z, k);

@@ -50,6 +50,8 @@ class SolverOptions:
     smax: float = 2.0                # occupancy of a full orbital (spin-restricted)
     n_states: int = 0                # finite T: Ritz pairs to converge (0 = block width - 4)
     occ_cut: float = 1e-12           # finite T: orbitals with f_i <= occ_cut * smax are left out
+    deflate: int = 0                 # FP64 adjoint: Ritz vectors above the included orbitals that
+                                     # deflate its preconditioner (0 = plain diagonal preconditioner)
 
 
 @dataclass
@@ -59,6 +61,8 @@ class OccState:
     occ: list
     eig: list
     mu: float | None = None          # None at T = 0
+    U: object = None                 # deflation block of the adjoint (N_f x nb copy) or None
+    theta: list | None = None        # its Ritz values
 
 
 @dataclass
@@ -101,7 +105,13 @@ class InverseProblem:
         self.stats = Stats()
         dev = X0.device
         self.work_eig = api._work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, self.nv, o.filter_prec), dev)
-        self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
+        if o.deflate > 0:
+            if o.adjoint_prec != "f64":
+                raise ValueError("the deflated adjoint solve is FP64 only")
+            self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED,
+                                                           min(64, self.nocc + o.deflate), "f64"), dev)
+        else:
+            self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
         self.work_lg = api._work(mesh.workspace_bytes(L.FE_OP_LOSS_GRAD, self.nocc), dev)
         self.work_ap = (api._work(mesh.workspace_bytes(L.FE_OP_ALONG_PSI, self.nocc), dev) if o.kT > 0 else None)
         self.last_loss = None
@@ -141,11 +151,26 @@ class InverseProblem:
             self.state = OccState(oc.n_incl, oc.occ[:oc.n_incl], r.eig[:oc.n_incl], oc.mu)
         else:
             self.state = OccState(self.nconv, [2.0] * self.nconv, r.eig[:self.nconv])
+        if o.deflate > 0:
+            self._deflation_block(r.eig)
         torch.cuda.current_stream().synchronize()
         self.stats.t_forward += time.perf_counter() - t0
         self.stats.passes.append(r.passes)
         self.stats.n_forward += 1
         return r
+
+    def _deflation_block(self, eig):
+        """The Ritz pairs above the included orbitals whose values clear every shift: a copy,
+        so that the next eigensolve may overwrite the block before the adjoint runs."""
+        st = self.state
+        top = max(st.eig)
+        j0 = st.n
+        while j0 < self.nv and eig[j0] <= top + 1e-8 * max(1.0, abs(top)):
+            j0 += 1                                  # degenerate with an included orbital
+        nb = min(self.opts.deflate, self.nv - j0, 64 - st.n)
+        if nb >= 1:
+            st.U = self.X[:, j0:j0 + nb].contiguous()
+            st.theta = list(eig[j0:j0 + nb])
 
     def psi(self):
         return self.X[:, :self.state.n].contiguous()
@@ -162,7 +187,8 @@ class InverseProblem:
         _, tol_adj = self.tolerances()
         t0 = time.perf_counter()
         Q, ar = api.adjoint_solve(self.mesh, self.v, Psi, st.eig, B, tol=tol_adj,
-                                  maxit=o.maxit_adj, prec=o.adjoint_prec, work=self.work_adj)
+                                  maxit=o.maxit_adj, prec=o.adjoint_prec, work=self.work_adj,
+                                  U=st.U, theta=st.theta)
         if o.kT > 0:
             api.adjoint_along_psi(self.mesh, Psi, st.eig, st.mu, o.kT, rho, self.rho_data, Q, smax=o.smax,
                                   work=self.work_ap)

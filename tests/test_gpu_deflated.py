@@ -1,0 +1,192 @@
+"""The deflated preconditioner of the adjoint solve (needs an MI355X).
+
+The preconditioner changes, the system (Eq. 20) does not, so every check is on the
+solution: against the oracle's gradient at small size, against the plain solve and the
+true residual on a coarse mesh of the 100-electron workload (50 columns that converge at
+different iterations, so the batch is compacted with the small deflation arrays), and
+with a deflation block that is no eigenvector at all (any such block leaves the
+preconditioner symmetric positive definite on the complement of the orbitals).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fe, ks  # noqa: E402
+from synth import random_block, workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(f"[deflated] {msg}", file=sys.stderr, flush=True)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+@functools.lru_cache(maxsize=None)
+def _small():
+    """The harmonic workload on its own mesh: oracle gradient and the GPU forward solve."""
+    from paper_2510_10529_amd import api
+    wl = workload(1)
+    om = fe.mesh3d(wl.p, wl.n, wl.half_width)
+    X = om.coords()
+    vf, vs = wl.v_fixed(X), wl.v_xc_target(X)
+    rho_d, _ = ks.target_density(om, vf + vs, wl.n_elec)
+    u = 0.4 * np.sin(X[:, 0]) * np.exp(-0.05 * np.sum(X * X, axis=1))
+    ev = ks.evaluate(om, vf + u, rho_d, wl.n_elec, method="bordered", extra=4)
+    m = api.Mesh(wl.p, wl.n, wl.half_width)
+    nv = wl.n_occ + wl.n_buf
+    Xb = _t(random_block(om.n_free, nv, 1))
+    v = _t(vf + u)
+    r = api.ks_eigensolve(m, v, Xb, wl.n_occ, wl.cheb_degree, 1e-10, 300)
+    assert r.status == 0, r
+    return wl, om, rho_d, ev, m, v, Xb, r
+
+
+def test_deflated_small_against_oracle():
+    from paper_2510_10529_amd import api
+    wl, om, rho_d, ev, m, v, X, r = _small()
+    k, nv = wl.n_occ, X.shape[1]
+    Psi = X[:, :k].contiguous()
+    U = X[:, k:nv].contiguous()
+    rho, B, loss = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d))
+    Q0, a0 = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-12, maxit=4000)
+    Q, ar = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-12, maxit=4000, U=U, theta=r.eig[k:nv])
+    _say(f"small: plain {a0.iters}, deflated {ar.iters}")
+    assert ar.status == 0, ar
+    assert max(ar.relres) < 1e-9, ar.relres
+    Qn = Q.cpu().numpy()
+    np.testing.assert_allclose(Psi.cpu().numpy().T @ Qn, 0, atol=1e-10 * np.abs(Qn).max())
+    g = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d), Q=Q).cpu().numpy()
+    rel = np.linalg.norm(g - ev.grad) / np.linalg.norm(ev.grad)
+    assert rel <= 1e-6, rel
+    assert max(ar.iters) <= max(a0.iters)
+
+
+def test_deflated_with_arbitrary_block_gives_same_solution():
+    """A random orthonormal block orthogonal to Psi, with made-up values above every shift:
+    the rate may suffer, the solution may not."""
+    from paper_2510_10529_amd import api
+    wl, om, rho_d, ev, m, v, X, r = _small()
+    k = wl.n_occ
+    Psi = X[:, :k].contiguous()
+    P = Psi.cpu().numpy()
+    R = random_block(om.n_free, 6, 77)
+    R -= P @ (P.T @ R)
+    R, _ = np.linalg.qr(R)
+    theta = [max(r.eig[:k]) + 0.3 + 0.7 * j for j in range(6)]
+    rho, B, loss = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d))
+    Q0, a0 = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-12, maxit=4000)
+    Q, ar = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-12, maxit=4000, U=_t(R), theta=theta)
+    assert ar.status == 0 and max(ar.relres) < 1e-9, ar
+    d = (Q - Q0).norm(dim=0) / Q0.norm(dim=0)
+    assert d.max().item() <= 1e-8, d
+
+
+@functools.lru_cache(maxsize=1)
+def _coarse():
+    """The 100-electron workload's potential on a coarse mesh (p = 5, 16 cells a side)."""
+    from paper_2510_10529_amd import api
+    wl = workload(5, p=5, n=16)
+    om = fe.mesh3d(wl.p, wl.n, wl.half_width)
+    X = om.coords()
+    vf, vs = wl.v_fixed(X), wl.v_xc_target(X)
+    m = api.Mesh(wl.p, wl.n, wl.half_width)
+    k, nv = wl.n_occ, wl.n_occ + wl.n_buf
+    Xt = _t(random_block(om.n_free, nv, 5))
+    rt = api.ks_eigensolve(m, _t(vf + vs), Xt, k, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+    assert rt.status == 0, rt
+    rho_d, _, _ = api.loss_grad(m, Xt[:, :k].contiguous(), [2.0] * k,
+                                torch.zeros(om.n_free, dtype=torch.float64, device=DEV), want_B=False)
+    v = _t(vf + 0.5 * vs)
+    Xb = Xt.clone()
+    r = api.ks_eigensolve(m, v, Xb, k, wl.cheb_degree, 1e-9, 400, prec="f32", switch_tol=1e-4)
+    assert r.status == 0, r
+    _say(f"coarse: N_f={om.n_free}, gap {r.eig[k] - r.eig[k - 1]:.3e}")
+    return wl, m, v, Xb, r, rho_d
+
+
+def test_deflated_coarse_mesh_compaction():
+    from paper_2510_10529_amd import api
+    wl, m, v, X, r, rho_d = _coarse()
+    k, nv = wl.n_occ, X.shape[1]
+    Psi = X[:, :k].contiguous()
+    U = X[:, k:nv].contiguous()
+    eps = list(r.eig[:k])
+    rho, B, loss = api.loss_grad(m, Psi, [2.0] * k, rho_d)
+    tol = 1e-10
+    Q0, a0 = api.adjoint_solve(m, v, Psi, eps, B, tol=tol, maxit=20000)
+    Q, ar = api.adjoint_solve(m, v, Psi, eps, B, tol=tol, maxit=20000, U=U, theta=r.eig[k:nv])
+    _say(f"coarse: plain max {max(a0.iters)} mean {np.mean(a0.iters):.1f} relres {max(a0.relres):.2e}; "
+         f"deflated max {max(ar.iters)} mean {np.mean(ar.iters):.1f} relres {max(ar.relres):.2e}")
+    assert a0.status == 0 and ar.status == 0
+    # the stop test is on the residual in the preconditioner's norm, which weighs the
+    # deflated directions by 1 / (theta - eps): the Euclidean residual is a few tol
+    assert max(ar.relres) <= 10 * tol
+    assert len(set(ar.iters)) > 4                      # columns stopped at different iterations
+    assert max(ar.iters) < max(a0.iters)
+    assert (Psi.T @ Q).abs().max().item() <= 1e-10 * Q.abs().max().item()
+    # both solve the same projected system to tol: their difference is bounded by the
+    # residuals through the inverse gap
+    d = ((Q - Q0).norm(dim=0) / Q0.norm(dim=0)).max().item()
+    assert d <= 1e-6, d
+    # true residual with the GPU operator
+    AQ = api.ks_apply(m, v, Q, shift=eps)
+    AQ = AQ - Psi @ (Psi.T @ AQ)
+    rel = ((B - AQ).norm(dim=0) / B.norm(dim=0)).max().item()
+    assert rel <= 10 * tol
+
+
+def test_deflated_rejects_bad_input():
+    from paper_2510_10529_amd import _lib, api
+    wl, om, rho_d, ev, m, v, X, r = _small()
+    k, nv = wl.n_occ, X.shape[1]
+    Psi = X[:, :k].contiguous()
+    U = X[:, k:nv].contiguous()
+    B = torch.zeros_like(Psi)
+    low = list(r.eig[k:nv])
+    low[0] = r.eig[k - 1]                                   # not above the top shift
+    with pytest.raises(_lib.FEError) as e:
+        api.adjoint_solve(m, v, Psi, r.eig[:k], B, U=U, theta=low)
+    assert e.value.status == _lib.FE_EINVAL
+    with pytest.raises(ValueError):
+        api.adjoint_solve(m, v, Psi, r.eig[:k], B, prec="f32", U=U, theta=r.eig[k:nv])
+    lib = _lib.load()
+    import ctypes as C
+    its = (C.c_int * k)()
+    rel = (C.c_double * k)()
+    wk = api._work(m.workspace_bytes(_lib.FE_OP_ADJOINT_DEFLATED, 64, "f64"), DEV)
+    st = lib.adjoint_solve_deflated(m.handle, api._ptr(v), api._ptr(Psi), api._host_doubles(r.eig[:k]), k,
+                                    api._ptr(U), api._host_doubles([1e3] * 64), 65 - k, api._ptr(B),
+                                    api._ptr(B), 1e-10, 10, its, rel, api._ptr(wk), None)
+    assert st == _lib.FE_EINVAL                              # nocc + nbuf > 64
+    assert m.workspace_bytes(_lib.FE_OP_ADJOINT_DEFLATED, 65, "f64") == 0
+
+
+def test_driver_deflate_option_same_gradient():
+    """The driver with and without deflation: the same loss and gradient."""
+    from paper_2510_10529_amd import inverse as inv
+    wl, om, rho_d, ev, m, v, X, r = _small()
+    Xc = om.coords()
+    vf = wl.v_fixed(Xc)
+    u = 0.4 * np.sin(Xc[:, 0]) * np.exp(-0.05 * np.sum(Xc * Xc, axis=1))
+    out = []
+    for d in (0, 6):
+        opts = inv.SolverOptions(degree=wl.cheb_degree, tol_eig=1e-10, tol_adj=1e-12, deflate=d)
+        prob = inv.InverseProblem(m, _t(vf), _t(rho_d), wl.n_elec,
+                                  _t(random_block(om.n_free, wl.n_occ + wl.n_buf, 1)), opts)
+        loss, g = prob.evaluate(_t(u))
+        assert (prob.state.U is not None) == (d > 0)
+        out.append((loss, g.cpu().numpy(), prob.stats.adj_iters[-1]))
+    _say(f"driver: adjoint iterations plain {out[0][2]}, deflated {out[1][2]}")
+    assert abs(out[0][0] - out[1][0]) <= 1e-12 * out[0][0]
+    rel = np.linalg.norm(out[1][1] - ev.grad) / np.linalg.norm(ev.grad)
+    assert rel <= 1e-6, rel
