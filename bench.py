@@ -90,17 +90,19 @@ def kernel_source_hash():
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(prec, workload_name):
+def read_traffic(prec, workload_name, deflate=0):
     """HBM bytes per launch of ks_apply in prec on this workload, from the rocprofv3 counter
     summary under profiles/ (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale, KiB per
-    dispatch), or None when there is none for the current kernel source."""
+    dispatch), or None when there is none for the current kernel source. The launch mix (and so
+    the average) depends on the adjoint's deflation, which is part of the key."""
     path = os.path.join(ROOT, "profiles", "ks_apply_traffic.txt")
     if not os.path.exists(path):
         return None
     want = kernel_source_hash()
     for line in open(path):
         f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
-        if f.get("workload") == workload_name and f.get("prec") == prec and f.get("src") == want:
+        if (f.get("workload") == workload_name and f.get("prec") == prec and f.get("src") == want
+                and int(f.get("deflate", "0")) == deflate):
             return 1024.0 * (float(f["fetch_kib"]) * float(f["fetch_scale"]) +
                              float(f["write_kib"]) * float(f["write_scale"]))
     return None
@@ -153,6 +155,10 @@ def main():
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kT", type=float, default=0.0, help="k_B T in Ha (0: zero temperature)")
+    ap.add_argument("--deflate", type=int, default=-1,
+                    help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
+                         "path (default: the block's buffer columns; 0: off). The FP64 path always keeps the "
+                         "diagonal preconditioner.")
     ap.add_argument("--frontend", action="store_true",
                     help="time the Hartree solve and the initial guess on the target density")
     ap.add_argument("--graded", type=float, default=0.0,
@@ -293,12 +299,13 @@ def main():
     step_len = 0.01
     results = {}
     common = dict(degree=wl.cheb_degree, tol_eig=1e-9, tol_adj=1e-10, maxpass=100, maxit_adj=20000)
+    deflate = nv - nocc if args.deflate < 0 else args.deflate
     if kT > 0:
         common.update(kT=kT, n_states=nconv)
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
         "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=1e-4,
-                                   recompute=True),
+                                   recompute=True, deflate=deflate),
     }
     for name in args.paths.split(","):
         log(f"path {name}")
@@ -335,7 +342,7 @@ def main():
     dom = max(tim, key=lambda p: tim[p][1])
     n_l, ms_l, b_l = tim[dom]
     achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
-    traffic = read_traffic(dom, wname)
+    traffic = read_traffic(dom, wname, deflate if "mixed" in results else 0)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
@@ -381,7 +388,8 @@ def main():
                    "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree,
                    **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {}),
                    **({"vxc_h": args.vxc_h, "vxc_vertices": vxc.n_vertices} if vxc is not None else {}),
-                   **({"graded_inner_h": args.graded, "growth": 1.35} if args.graded > 0 else {})},
+                   **({"graded_inner_h": args.graded, "growth": 1.35} if args.graded > 0 else {}),
+                   **({"adjoint_deflation": deflate} if "mixed" in results and deflate > 0 else {})},
         "ks_apply_GBps_f32": gbs32,
         "ks_apply_GBps_f64": gbs64,
         "ks_apply_ms_f32": ms32,

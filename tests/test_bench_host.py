@@ -23,8 +23,11 @@ def test_traffic_follows_kernel_source(tmp_path, monkeypatch):
     h = b.kernel_source_hash()
     (tmp_path / "profiles" / "ks_apply_traffic.txt").write_text(
         "# comment\n"
-        f"workload=w1 prec=f64 src={h} fetch_kib=100 write_kib=50 fetch_scale=2.0 write_scale=1.0 launches=3\n")
+        f"workload=w1 prec=f64 src={h} fetch_kib=100 write_kib=50 fetch_scale=2.0 write_scale=1.0 launches=3\n"
+        f"workload=w1 prec=f64 src={h} deflate=10 fetch_kib=70 write_kib=40 fetch_scale=2.0 write_scale=1.0\n")
     assert b.read_traffic("f64", "w1") == 1024.0 * (100 * 2.0 + 50 * 1.0)
+    assert b.read_traffic("f64", "w1", 10) == 1024.0 * (70 * 2.0 + 40 * 1.0)   # another launch mix
+    assert b.read_traffic("f64", "w1", 6) is None
     assert b.read_traffic("f32", "w1") is None
     assert b.read_traffic("f64", "other") is None
     (csrc / "apply.hip").write_text("kernel v2\n")          # the kernel changed since the counters
