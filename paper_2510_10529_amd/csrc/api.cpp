@@ -115,7 +115,14 @@ fe_status filter_impl(const Mesh& m, const double* v, int degree, double a, doub
     sigma = sigma_new;
     cur = 1 - cur;
   }
-  if (cur == 1) INVDFT_HIP(hipMemcpyAsync(X, work, (size_t)m.nf * ld * elem_size(prec), hipMemcpyDeviceToDevice, s));
+  if (cur == 1) {
+    const size_t es = elem_size(prec);
+    if (nv == ld) {
+      INVDFT_HIP(hipMemcpyAsync(X, work, (size_t)m.nf * ld * es, hipMemcpyDeviceToDevice, s));
+    } else {  // a sub-block of columns: copy only those
+      INVDFT_HIP(hipMemcpy2DAsync(X, ld * es, work, ld * es, nv * es, m.nf, hipMemcpyDeviceToDevice, s));
+    }
+  }
   return FE_OK;
 }
 
@@ -835,12 +842,28 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "ks_eigensolve: degenerate filter interval");
     if (low && (rmax <= switch_tol || rmax > 0.5 * rprev)) low = false;
     rprev = rmax;
+    // Locking: the leading Ritz pairs that already meet tol are not filtered again (rounded
+    // down to a multiple of 8 columns, so that the filtered sub-block keeps 16-byte aligned
+    // rows in both precisions). Rayleigh-Ritz still runs over the whole block, so a locked
+    // pair that drifts above tol is filtered again on the next pass.
+    int j0 = 0;
+    while (j0 < nocc && resnorm_h[j0] <= tol) ++j0;
+    j0 &= ~7;
+    const int nfilt = nv - j0;
     if (low) {
       if ((st = cast_block_to_f32(X, w.Xf, (int64_t)m.nf * ld, s)) != FE_OK) return st;
-      if ((st = filter_impl(m, v, degree, a, b, a0, w.Xf, nv, ld, FE_F32, w.filt, s)) != FE_OK) return st;
-      if ((st = cast_block_to_f64(w.Xf, X, (int64_t)m.nf * ld, s)) != FE_OK) return st;
+      if ((st = filter_impl(m, v, degree, a, b, a0, w.Xf + j0, nfilt, ld, FE_F32,
+                            static_cast<float*>(static_cast<void*>(w.filt)) + j0, s)) != FE_OK)
+        return st;
+      if (j0 == 0) {
+        if ((st = cast_block_to_f64(w.Xf, X, (int64_t)m.nf * ld, s)) != FE_OK) return st;
+      } else if ((st = cast_cols_to_f64(w.Xf, X, m.nf, ld, j0, s)) != FE_OK) {
+        return st;
+      }
     } else {
-      if ((st = filter_impl(m, v, degree, a, b, a0, X, nv, ld, FE_F64, w.filt, s)) != FE_OK) return st;
+      if ((st = filter_impl(m, v, degree, a, b, a0, X + j0, nfilt, ld, FE_F64,
+                            static_cast<double*>(static_cast<void*>(w.filt)) + j0, s)) != FE_OK)
+        return st;
     }
     if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
     ++pass;

@@ -294,6 +294,18 @@ __global__ void cast_kernel(const TS* __restrict__ src, TD* __restrict__ dst, lo
     dst[i] = (TD)src[i];
 }
 
+// columns [c0, ld) of an nrow x ld row-major block (the trailing columns of every row)
+template <typename TS, typename TD>
+__global__ void cast_cols_kernel(const TS* __restrict__ src, TD* __restrict__ dst, long long nrow, int ld, int c0) {
+  const int w = ld - c0;
+  const long long n = nrow * w;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const long long a = e / w;
+    const long long i = a * ld + c0 + (e - a * w);
+    dst[i] = (TD)src[i];
+  }
+}
+
 __global__ void axpby_kernel(double alpha, const double* __restrict__ x, double beta, double* __restrict__ y,
                              long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -456,6 +468,14 @@ fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStr
 fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL((cast_kernel<float, double>), dim3(stream_grid(count)), dim3(256), 0, s, src, dst,
                      (long long)count);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status cast_cols_to_f64(const float* src, double* dst, int64_t nrow, int ld, int c0, hipStream_t s) {
+  if (c0 < 0 || c0 >= ld) return fail(FE_EINVAL, "cast_cols: column range");
+  hipLaunchKernelGGL((cast_cols_kernel<float, double>), dim3(stream_grid(nrow * (ld - c0))), dim3(256), 0, s, src, dst,
+                     (long long)nrow, ld, c0);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

@@ -114,6 +114,8 @@ fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t 
 // Kernels used by the Krylov and loss/gradient code (defined in blockops.hip).
 fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
 fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s);
+// columns [c0, ld) of an nrow x ld block (row pitch ld in both)
+fe_status cast_cols_to_f64(const float* src, double* dst, int64_t nrow, int ld, int c0, hipStream_t s);
 fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s);
 fe_status fill(double* y, double val, int64_t n, hipStream_t s);
 
