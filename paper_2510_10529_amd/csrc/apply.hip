@@ -1025,8 +1025,10 @@ static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec
 
 fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s) {
   if (!g_timing.on || m.nf == 0) return launch_apply_untimed(m, a, prec, s);
+  // algorithmic bytes: X read, Y written, Z read when given (the Chebyshev term), v read
+  const double blocks = a.Z ? 3.0 : 2.0;
   TimedLaunch t{g_timing.take(), g_timing.take(), (int)prec,
-                (double)m.nf * (2.0 * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0)};
+                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0)};
   if (!t.start || !t.stop) return fail(FE_EDEVICE, "ks_apply timing: hipEventCreate failed");
   INVDFT_HIP(hipEventRecord(t.start, s));
   const fe_status st = launch_apply_untimed(m, a, prec, s);
