@@ -1,0 +1,86 @@
+"""Locking in the Chebyshev-filtered subspace iteration (needs an MI355X).
+
+Converged leading Ritz pairs are not filtered again. In a reduced-precision pass only the
+filtered columns go through FP32, so the locked pairs keep FP64 accuracy; a pass that cast
+the whole block would leave them at the FP32 rounding level (residuals near 1e-6).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from synth import random_block, workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+OK = (0, 6)          # FE_OK, or FE_EGAP: the coarse mesh's gap at the Fermi level is not the point here
+
+
+def _say(msg):
+    print(f"[locking] {msg}", file=sys.stderr, flush=True)
+
+
+@functools.lru_cache(maxsize=1)
+def _converged():
+    """The 100-electron potential on a small mesh (p = 4, 8 cells a side), solved in FP64."""
+    from paper_2510_10529_amd import api
+    from oracle import fe
+    wl = workload(5, p=4, n=8)
+    om = fe.mesh3d(wl.p, wl.n, wl.half_width)
+    X = om.coords()
+    m = api.Mesh(wl.p, wl.n, wl.half_width)
+    v = torch.tensor(wl.v_fixed(X) + wl.v_xc_target(X), device=DEV)
+    k, nv = wl.n_occ, wl.n_occ + wl.n_buf
+    Xb = torch.tensor(random_block(om.n_free, nv, 9), device=DEV)
+    r = api.ks_eigensolve(m, v, Xb, k, wl.cheb_degree, 1e-11, 400)
+    assert r.status in OK, r
+    return wl, m, v, Xb, r
+
+
+def test_fp32_pass_keeps_locked_columns_in_fp64():
+    from paper_2510_10529_amd import api
+    wl, m, v, X, r = _converged()
+    k, nv = wl.n_occ, X.shape[1]
+    tol = 1e-9
+    # the leading 16 columns converged, the rest perturbed away from the eigenvectors
+    Y = X.clone()
+    noise = torch.tensor(random_block(X.shape[0], nv - 16, 10), device=DEV)
+    Y[:, 16:] += 1e-2 * noise / noise.norm(dim=0)
+    r0 = api.ks_eigensolve(m, v, Y.clone(), k, wl.cheb_degree, tol, 0, prec="f32", switch_tol=1e-12)
+    lead = max(r0.res[:16])
+    _say(f"before: leading max residual {lead:.1e}, rest max {max(r0.res[16:k]):.1e}")
+    assert lead <= tol and max(r0.res[16:k]) > tol          # 16 locked columns, the rest filtered
+    # exactly one FP32 pass (switch tolerance below every residual, no stagnation test yet)
+    r1 = api.ks_eigensolve(m, v, Y, k, wl.cheb_degree, tol, 1, prec="f32", switch_tol=1e-12)
+    assert r1.passes == 1
+    _say(f"after one FP32 pass: leading max residual {max(r1.res[:16]):.1e}")
+    assert max(r1.res[:16]) <= 10 * tol
+    np.testing.assert_allclose(r1.eig[:16], r.eig[:16], rtol=0, atol=1e-10)
+
+
+def test_locking_reaches_same_eigenpairs():
+    """A warm-started solve after a potential change, in each precision: the same Ritz values as a
+    cold FP64 solve, and orthonormal orbitals."""
+    from paper_2510_10529_amd import api
+    from oracle import fe
+    wl, m, v, X, r = _converged()
+    k = wl.n_occ
+    om = fe.mesh3d(wl.p, wl.n, wl.half_width)
+    xs = om.coords()[:, 0]
+    v2 = v + torch.tensor(0.05 * np.cos(0.4 * xs), device=DEV)
+    cold = api.ks_eigensolve(m, v2, torch.tensor(random_block(X.shape[0], X.shape[1], 11), device=DEV),
+                             k, wl.cheb_degree, 1e-10, 400)
+    assert cold.status in OK, cold
+    for prec in ("f64", "f32"):
+        Y = X.clone()
+        rw = api.ks_eigensolve(m, v2, Y, k, wl.cheb_degree, 1e-10, 400, prec=prec, switch_tol=1e-4)
+        assert rw.status in OK, rw
+        _say(f"{prec}: warm {rw.passes} passes, cold {cold.passes}")
+        np.testing.assert_allclose(rw.eig[:k], cold.eig[:k], rtol=0, atol=1e-9)
+        Psi = Y[:, :k]
+        G = (Psi.T @ Psi).cpu().numpy()
+        np.testing.assert_allclose(G, np.eye(k), atol=1e-11)
