@@ -169,7 +169,11 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
  * bounds are b = kinetic bound + max(v), a = largest Ritz value, a0 = smallest.
  * prec selects the filter precision (FE_F64 / FE_F32; FE_EINVAL otherwise); with a
  * reduced precision the passes switch to FP64 once the residual is below
- * `switch_tol`, so the final accuracy is FP64's. Rayleigh-Ritz is FP64.
+ * `switch_tol` (or stops falling), so the final accuracy is FP64's. Rayleigh-Ritz
+ * is FP64. Locking: a pass filters only the columns from the first leading Ritz
+ * pair whose residual is above tol (rounded down to a multiple of 8); the pairs
+ * before it are left as they are (also in FP64 during a reduced-precision pass)
+ * and still enter the Rayleigh-Ritz of the whole block.
  *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.
  *   passes_h: number of passes done (nullable).
  * Returns FE_ENOCONV if maxpass was reached (X, eig_h, resnorm_h valid).
