@@ -26,10 +26,12 @@ def _say(msg):
 
 @functools.lru_cache(maxsize=1)
 def _converged():
-    """The 100-electron potential on a small mesh (p = 4, 8 cells a side), solved in FP64."""
+    """The 100-electron potential on a coarse mesh (p = 5, 16 cells a side), solved in FP64.
+    (Much coarser meshes put the operator's upper bound so close to the occupied spectrum that
+    one degree-40 pass from a random block amplifies the lowest direction beyond FP64's range.)"""
     from paper_2510_10529_amd import api
     from oracle import fe
-    wl = workload(5, p=4, n=8)
+    wl = workload(5, p=5, n=16)
     om = fe.mesh3d(wl.p, wl.n, wl.half_width)
     X = om.coords()
     m = api.Mesh(wl.p, wl.n, wl.half_width)
