@@ -155,6 +155,8 @@ def main():
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kT", type=float, default=0.0, help="k_B T in Ha (0: zero temperature)")
+    ap.add_argument("--switch-tol", type=float, default=3e-4,
+                    help="mixed path: FP32 filter passes while the largest occupied residual is above this")
     ap.add_argument("--deflate", type=int, default=-1,
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
                          "path (default: the block's buffer columns; 0: off). The FP64 path always keeps the "
@@ -304,7 +306,7 @@ def main():
         common.update(kT=kT, n_states=nconv)
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
-        "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=1e-4,
+        "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=args.switch_tol,
                                    recompute=True, deflate=deflate),
     }
     for name in args.paths.split(","):

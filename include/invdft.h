@@ -173,7 +173,8 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
  * is FP64. Locking: a pass filters only the columns from the first leading Ritz
  * pair whose residual is above tol (rounded down to a multiple of 8); the pairs
  * before it are left as they are (also in FP64 during a reduced-precision pass)
- * and still enter the Rayleigh-Ritz of the whole block.
+ * and still enter the Rayleigh-Ritz of the whole block. A reduced-precision pass
+ * locks against max(tol, switch_tol) instead of tol.
  *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.
  *   passes_h: number of passes done (nullable).
  * Returns FE_ENOCONV if maxpass was reached (X, eig_h, resnorm_h valid).

@@ -845,9 +845,12 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     // Locking: the leading Ritz pairs that already meet tol are not filtered again (rounded
     // down to a multiple of 8 columns, so that the filtered sub-block keeps 16-byte aligned
     // rows in both precisions). Rayleigh-Ritz still runs over the whole block, so a locked
-    // pair that drifts above tol is filtered again on the next pass.
+    // pair that drifts above tol is filtered again on the next pass. A reduced-precision
+    // pass also leaves alone the pairs already below switch_tol: it could not improve them,
+    // only round them to its own level.
+    const double lock_tol = low ? std::max(tol, switch_tol) : tol;
     int j0 = 0;
-    while (j0 < nocc && resnorm_h[j0] <= tol) ++j0;
+    while (j0 < nocc && resnorm_h[j0] <= lock_tol) ++j0;
     j0 &= ~7;
     const int nfilt = nv - j0;
     if (low) {
