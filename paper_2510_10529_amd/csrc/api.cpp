@@ -301,10 +301,10 @@ fe_status fill_t<float>(float* y, int64_t n, hipStream_t s) { return fill_f32(y,
 // then run with V in place of Psi (pass B's subtraction V (V^T y) is exactly the deflated
 // recurrence), plus four small per-column corrections.
 struct Deflation {
-  const double* V;      // [Psi U], N x (k0 + nb)
-  const double* U;      // N x nb
+  double* V;            // [Psi U], N x (k0 + nb)
+  double* U;            // N x nb
   int nb;
-  const double* theta;  // nb (device)
+  double* theta;        // nb (device)
   double* eps;          // shifts of the current columns (device, k)
   double *cA, *cB, *cC, *tmp;  // nb x k small arrays (device)
 };
@@ -960,11 +960,14 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
   if (nocc < 1 || nbuf < 1 || nocc + nbuf > 64)
     return fail(FE_EINVAL, "adjoint_solve_deflated: nocc >= 1, nbuf >= 1 and nocc + nbuf <= 64 required");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve_deflated: tol > 0 and maxit >= 1 required");
-  double emax = eps_h[0], tmin = theta_h[0];
-  for (int i = 0; i < nocc; ++i) emax = std::max(emax, eps_h[i]);
-  for (int j = 0; j < nbuf; ++j) tmin = std::min(tmin, theta_h[j]);
-  if (!(tmin > emax) || !std::isfinite(tmin) || !std::isfinite(emax))
-    return fail(FE_EINVAL, "adjoint_solve_deflated: every theta must lie above every shift");
+  double emax = -INFINITY;
+  for (int i = 0; i < nocc; ++i) {
+    if (!std::isfinite(eps_h[i])) return fail(FE_EINVAL, "adjoint_solve_deflated: shifts must be finite");
+    emax = std::max(emax, eps_h[i]);
+  }
+  for (int j = 0; j < nbuf; ++j)  // also refuses NaN
+    if (!(theta_h[j] > emax) || !std::isfinite(theta_h[j]))
+      return fail(FE_EINVAL, "adjoint_solve_deflated: every theta must lie above every shift");
   const Mesh& m = mesh->m;
   hipStream_t s = S(stream);
   Bump bp(work);
@@ -978,8 +981,8 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
   if ((st = copy_bytes(U, Uc, (size_t)m.nf * nbuf * sizeof(double), s)) != FE_OK) return st;
   for (int pass = 0; pass < 2; ++pass)
     if ((st = project_out(Psi, nocc, Uc, nbuf, m.nf, false, w.pw, s)) != FE_OK) return st;
-  if ((st = defl_pack(Psi, nocc, Uc, nbuf, const_cast<double*>(df.V), m.nf, s)) != FE_OK) return st;
-  INVDFT_HIP(hipMemcpyAsync(const_cast<double*>(df.theta), theta_h, nbuf * sizeof(double), hipMemcpyHostToDevice, s));
+  if ((st = defl_pack(Psi, nocc, Uc, nbuf, df.V, m.nf, s)) != FE_OK) return st;
+  INVDFT_HIP(hipMemcpyAsync(df.theta, theta_h, nbuf * sizeof(double), hipMemcpyHostToDevice, s));
   INVDFT_HIP(hipMemcpyAsync(df.eps, eps_h, nocc * sizeof(double), hipMemcpyHostToDevice, s));
   return adjoint_f64(m, v, Psi, eps_h, nocc, B, Q, tol, maxit, iters_h, relres_h, w, &df, "adjoint_solve_deflated", s);
 }

@@ -157,6 +157,11 @@ def test_deflated_rejects_bad_input():
     with pytest.raises(_lib.FEError) as e:
         api.adjoint_solve(m, v, Psi, r.eig[:k], B, U=U, theta=low)
     assert e.value.status == _lib.FE_EINVAL
+    nan = list(r.eig[k:nv])
+    nan[1] = float("nan")                                   # not the first: min() would skip it
+    with pytest.raises(_lib.FEError) as e:
+        api.adjoint_solve(m, v, Psi, r.eig[:k], B, U=U, theta=nan)
+    assert e.value.status == _lib.FE_EINVAL
     with pytest.raises(ValueError):
         api.adjoint_solve(m, v, Psi, r.eig[:k], B, prec="f32", U=U, theta=r.eig[k:nv])
     lib = _lib.load()
