@@ -68,7 +68,8 @@ def test_deflated_small_against_oracle():
     g = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d), Q=Q).cpu().numpy()
     rel = np.linalg.norm(g - ev.grad) / np.linalg.norm(ev.grad)
     assert rel <= 1e-6, rel
-    assert max(ar.iters) <= max(a0.iters)
+    # (the iteration gain is asserted on the molecules below; this small harmonic case has
+    # few slow directions, and the refinement round can cost about what deflation saves)
 
 
 def test_deflated_with_arbitrary_block_gives_same_solution():
@@ -129,8 +130,8 @@ def test_deflated_coarse_mesh_compaction():
          f"deflated max {max(ar.iters)} mean {np.mean(ar.iters):.1f} relres {max(ar.relres):.2e}")
     assert a0.status == 0 and ar.status == 0
     # the stop test is on the residual in the preconditioner's norm, which weighs the
-    # deflated directions by 1 / (theta - eps): the Euclidean residual is a few tol
-    assert max(ar.relres) <= 10 * tol
+    # deflated directions by 1 / (theta - eps); refinement rounds bring every column within 2 tol
+    assert max(ar.relres) <= 2 * tol
     assert len(set(ar.iters)) > 4                      # columns stopped at different iterations
     assert max(ar.iters) < max(a0.iters)
     assert (Psi.T @ Q).abs().max().item() <= 1e-10 * Q.abs().max().item()
@@ -142,7 +143,7 @@ def test_deflated_coarse_mesh_compaction():
     AQ = api.ks_apply(m, v, Q, shift=eps)
     AQ = AQ - Psi @ (Psi.T @ AQ)
     rel = ((B - AQ).norm(dim=0) / B.norm(dim=0)).max().item()
-    assert rel <= 10 * tol
+    assert rel <= 2 * tol
 
 
 def test_deflated_rejects_bad_input():
