@@ -124,7 +124,10 @@ fe_status fe_mesh_destroy(fe_mesh mesh);
 /* Bytes of device work buffer an operation needs for a block of nv columns
  * (nv = nocc for FE_OP_ADJOINT_SOLVE and FE_OP_LOSS_GRAD, nv = n for
  * FE_OP_ALONG_PSI, nv = 1 for FE_OP_POISSON, nv = nocc + nbuf for
- * FE_OP_ADJOINT_DEFLATED, FP64 only). 0 on bad input. */
+ * FE_OP_ADJOINT_DEFLATED, FP64 only). For FE_OP_CHEB_FILTER,
+ * FE_OP_RAYLEIGH_RITZ and FE_OP_EIGENSOLVE the work blocks share the caller's
+ * row pitch, so pass the block's leading dimension ld (>= its column count) as
+ * nv. 0 on bad input. */
 size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec);
 
 const char* fe_last_error(void);
@@ -146,7 +149,7 @@ fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const v
  * (Sec. 3.2.2; Zhou and Saad 2007): with c = (a+b)/2, e = (b-a)/2,
  *   p_m(lambda) = T_m((lambda - c)/e) / T_m((a0 - c)/e),
  * which damps [a, b] and keeps the columns O(1) near a0 < a.
- *   degree >= 1, a < b, a0 < a. work: fe_workspace_bytes(FE_OP_CHEB_FILTER).
+ *   degree >= 1, a < b, a0 < a. work: fe_workspace_bytes(FE_OP_CHEB_FILTER, ld).
  * prec: FE_F64 or FE_F32 (X's type follows prec; FE_EINVAL otherwise). */
 fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, double b, double a0,
                       void* X, int nv, int ld, fe_prec prec, void* work, void* stream);
@@ -157,7 +160,7 @@ fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, doubl
  * X <- X L^{-T} V (orthonormal Ritz vectors, ascending Ritz values in eig_h),
  * resnorm_h[i] = || H~ x_i - eig_i x_i ||_2 (nullable).
  * On FE_ENOTPD (S not positive definite) X is left unchanged.
- * work: fe_workspace_bytes(FE_OP_RAYLEIGH_RITZ). Synchronises the stream. */
+ * work: fe_workspace_bytes(FE_OP_RAYLEIGH_RITZ, ld). Synchronises the stream. */
 fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h, double* resnorm_h,
                         int nv, int ld, void* work, void* stream);
 
@@ -178,7 +181,7 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
  *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.
  *   passes_h: number of passes done (nullable).
  * Returns FE_ENOCONV if maxpass was reached (X, eig_h, resnorm_h valid).
- * work: fe_workspace_bytes(FE_OP_EIGENSOLVE, nv, prec). */
+ * work: fe_workspace_bytes(FE_OP_EIGENSOLVE, ld, prec). */
 fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld, int nocc,
                         int degree, double tol, int maxpass, fe_prec prec, double switch_tol,
                         double* eig_h, double* resnorm_h, int* passes_h, void* work, void* stream);
@@ -190,7 +193,10 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
  * iteration makes one ks_apply with per-column shifts. The operator and the
  * preconditioner T = P diag(K~_aa/2)^{-1} P (P = I - Psi Psi^T, the inverse
  * kinetic diagonal) are both restricted to the complement of the occupied
- * orbitals. A column stops when its estimated relative residual is <= tol.
+ * orbitals. MINRES stops a column on its residual estimate in the
+ * preconditioner's norm (relative to b, <= tol); in FP64 every column is then
+ * held to the Euclidean bar ||b_i - (H~ - eps_i) q_i||_2 <= 2 tol ||b_i||_2:
+ * columns above it are refined on their true residual (at most three rounds).
  *   Psi: N_f x nocc orthonormal occupied orbitals (ld = nocc), eps_h: nocc
  *   host doubles, B: right-hand sides (N_f x nocc, orthogonal to Psi), Q: out.
  *   iters_h (nocc ints) and relres_h (nocc doubles: true ||b - A q|| / ||b||,
@@ -199,7 +205,9 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
  * max(tol, 1e-4)) with FP64 iterative refinement (residuals and updates of Q in
  * FP64). nocc <= 64. Columns that have converged are dropped from the batch.
  * Psi, B, Q and work must be 16-byte aligned (FE_EINVAL otherwise).
- * Returns FE_ENOCONV when some column did not reach tol in maxit iterations.
+ * maxit bounds the whole FP64 solve (first solve and refinement rounds
+ * together, counted in iterations of the slowest column). Returns FE_ENOCONV
+ * when some column misses the bar within maxit (Q, iters_h, relres_h filled).
  * work: fe_workspace_bytes(FE_OP_ADJOINT_SOLVE, nocc, prec). Synchronises. */
 fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h,
                         int nocc, const double* B, double* Q, double tol, int maxit, int* iters_h,
@@ -222,9 +230,14 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
  *   Psi projected out is used, the caller's U is not modified);
  *   theta_h: nbuf host doubles, each strictly greater than every eps_h[i].
  * Other arguments as adjoint_solve. 1 <= nocc, 1 <= nbuf, nocc + nbuf <= 64.
+ * The result is held to the same Euclidean bar as adjoint_solve (FP64):
+ * ||b_i - (H~ - eps_i) q_i||_2 <= 2 tol ||b_i||_2 for every column. Since the
+ * preconditioner's norm weighs the U directions by 1 / (theta_j - eps_i), the
+ * first solve stops at tol / 6 and columns still above the bar are refined.
  * FE_EINVAL on bad sizes, NULL or unaligned pointers, or theta not above every
- * shift; FE_ENOCONV when some column did not reach tol in maxit iterations
- * (Q, iters_h and relres_h are filled all the same).
+ * shift; FE_ENOCONV when some column misses the bar within maxit iterations
+ * (one budget for the first solve and the refinement rounds; Q, iters_h and
+ * relres_h are filled all the same).
  * work: fe_workspace_bytes(FE_OP_ADJOINT_DEFLATED, nocc + nbuf, FE_F64).
  * Synchronises the stream. */
 fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Psi,

@@ -12,7 +12,7 @@ finite-element inverse DFT (Sec. 2 and Sec. 3.2):
                 assembled sparse matrix and as Kronecker-factored 1-D applies.
 * ``ks``      — forward eigenproblem (Eq. 19), density (Eq. 4), loss (Eq. 1),
                 adjoint right-hand side and solution (Eqs. 7, 10, 20), gradient
-                (Eqs. 11, 22), central finite differences, L-BFGS (Eq. 21).
+                (Eqs. 11, 22), central finite differences.
 * ``chfsi``   — the Chebyshev filter polynomial and Rayleigh-Ritz projection
                 (Sec. 3.2.2, Eqs. 23-24) by their plain definitions.
 * ``vxcmesh`` — the XC potential on its own linear mesh (Eq. 14): the prolongation

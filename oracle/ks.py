@@ -234,16 +234,3 @@ def fd_directional(mesh: fe.Mesh3D, v: np.ndarray, rho_data: np.ndarray, n_elec:
     lp = loss_only(mesh, v + h * d, rho_data, n_elec)
     lm = loss_only(mesh, v - h * d, rho_data, n_elec)
     return (lp - lm) / (2.0 * h)
-
-
-def lbfgs(mesh: fe.Mesh3D, v_fixed: np.ndarray, rho_data: np.ndarray, n_elec: int,
-          u0: np.ndarray, maxiter: int = 30, history: int = 10):
-    """L-BFGS on the nodal XC potential (Eq. 21) with SciPy's implementation."""
-    from scipy.optimize import minimize
-
-    def fun(u):
-        ev = evaluate(mesh, v_fixed + u, rho_data, n_elec)
-        return ev.loss, ev.grad
-
-    return minimize(fun, u0, jac=True, method="L-BFGS-B",
-                    options={"maxcor": history, "maxiter": maxiter, "gtol": 0.0, "ftol": 0.0})

@@ -9,10 +9,17 @@ with v_x the Slater (local-density) exchange potential of the spin-unpolarised g
     v_x = -(3 rho / pi)^{1/3}     (the derivative of rho e_x, e_x = -(3/4)(3 rho / pi)^{1/3}),
 and the Perdew-Wang 1992 correlation of the unpolarised gas, r_s = (3 / (4 pi rho))^{1/3},
     e_c(r_s) = -2A (1 + a1 r_s) ln(1 + 1 / (2A (b1 r_s^{1/2} + b2 r_s + b3 r_s^{3/2} + b4 r_s^2))),
-    v_c = e_c - (r_s / 3) de_c/dr_s,
-A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294 (the
-paper's table of parameters for the unpolarised case, p = 1). The LB94 exchange of
-the paper's recommended default needs density gradients and is not reproduced here.
+    v_c = e_c - (r_s / 3) de_c/dr_s.
+The paper names PW92 for v_0 of Eq. 25 but prints none of its parameters; the values below are the
+published unpolarised-gas parameters of J. P. Perdew and Y. Wang, Phys. Rev. B 45, 13244 (1992):
+A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294 (exponent p = 1).
+The fit is built to reproduce the limits of the electron gas: the high-density expansion
+e_c = A ln r_s - c1 + O(r_s ln r_s) with A = (1 - ln 2)/pi^2 and c1 = 0.046644, with no
+r_s^{1/2} term (so b1 = e^{-c1/2A}/2A and b2 = 2 A b1^2), and the low-density expansion
+e_c = -d0/r_s + d1/r_s^{3/2} with d0 = a1/b4 = 0.4335 and d1 = a1 b3/b4^2 = 1.4408. The tests
+pin every constant by these relations.
+LB94 exchange (van Leeuwen and Baerends 1994, the paper's recommended choice) uses the published
+beta = 0.05; its design property, the -1/r tail, does not depend on beta, so beta is unpinned.
 Densities below 1e-30 are treated as empty (v_x = v_c = 0 there).
 """
 from __future__ import annotations

@@ -155,22 +155,27 @@ def ks_apply(mesh: Mesh, v, X, Y=None, shift=None, prec: str = "f64"):
     return Y
 
 
-def cheb_filter(mesh: Mesh, v, degree: int, a: float, b: float, a0: float, X, prec: str = "f64", work=None):
-    nv = X.shape[1]
+def cheb_filter(mesh: Mesh, v, degree: int, a: float, b: float, a0: float, X, prec: str = "f64", work=None,
+                nv=None):
+    """Filters the first nv columns (default: all) of X, whose row pitch is X.shape[1]."""
+    ld = X.shape[1]
+    nv = ld if nv is None else int(nv)
     if work is None:
-        work = _work(mesh.workspace_bytes(L.FE_OP_CHEB_FILTER, nv, prec), X.device)
-    L.check(L.load().cheb_filter(mesh.handle, _ptr(v), int(degree), float(a), float(b), float(a0), _ptr(X), nv, nv,
+        work = _work(mesh.workspace_bytes(L.FE_OP_CHEB_FILTER, ld, prec), X.device)
+    L.check(L.load().cheb_filter(mesh.handle, _ptr(v), int(degree), float(a), float(b), float(a0), _ptr(X), nv, ld,
                                  PREC[prec], _ptr(work), _stream()), "cheb_filter")
     return X
 
 
-def rayleigh_ritz(mesh: Mesh, v, X, work=None):
-    nv = X.shape[1]
+def rayleigh_ritz(mesh: Mesh, v, X, work=None, nv=None):
+    """Rayleigh-Ritz on the first nv columns (default: all) of X, whose row pitch is X.shape[1]."""
+    ld = X.shape[1]
+    nv = ld if nv is None else int(nv)
     if work is None:
-        work = _work(mesh.workspace_bytes(L.FE_OP_RAYLEIGH_RITZ, nv), X.device)
+        work = _work(mesh.workspace_bytes(L.FE_OP_RAYLEIGH_RITZ, ld), X.device)
     eig = (C.c_double * nv)()
     res = (C.c_double * nv)()
-    L.check(L.load().rayleigh_ritz(mesh.handle, _ptr(v), _ptr(X), eig, res, nv, nv, _ptr(work), _stream()),
+    L.check(L.load().rayleigh_ritz(mesh.handle, _ptr(v), _ptr(X), eig, res, nv, ld, _ptr(work), _stream()),
             "rayleigh_ritz")
     return list(eig), list(res)
 
@@ -184,14 +189,16 @@ class EigResult:
 
 
 def ks_eigensolve(mesh: Mesh, v, X, nocc: int, degree: int, tol: float, maxpass: int, prec: str = "f64",
-                  switch_tol: float = 1e-5, work=None, allow=(L.FE_ENOCONV, L.FE_EGAP)) -> EigResult:
-    nv = X.shape[1]
+                  switch_tol: float = 1e-5, work=None, allow=(L.FE_ENOCONV, L.FE_EGAP), nv=None) -> EigResult:
+    """ChFSI on the first nv columns (default: all) of X, whose row pitch is X.shape[1]."""
+    ld = X.shape[1]
+    nv = ld if nv is None else int(nv)
     if work is None:
-        work = _work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, nv, prec), X.device)
+        work = _work(mesh.workspace_bytes(L.FE_OP_EIGENSOLVE, ld, prec), X.device)
     eig = (C.c_double * nv)()
     res = (C.c_double * nv)()
     passes = C.c_int()
-    st = L.load().ks_eigensolve(mesh.handle, _ptr(v), _ptr(X), nv, nv, int(nocc), int(degree), float(tol),
+    st = L.load().ks_eigensolve(mesh.handle, _ptr(v), _ptr(X), nv, ld, int(nocc), int(degree), float(tol),
                                 int(maxpass), PREC[prec], float(switch_tol), eig, res, C.byref(passes), _ptr(work),
                                 _stream())
     L.check(st, "ks_eigensolve", allow=allow)

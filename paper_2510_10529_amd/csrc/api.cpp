@@ -248,6 +248,8 @@ struct MRWork {
   // FP32 refinement extras
   float* Psif;    // FP32 copy of Psi
   double *R64, *Y64;
+  // FP64 refinement on the true residual: its right-hand side, correction and column mask
+  double *rb, *dq, *mask;
 };
 
 MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
@@ -274,6 +276,10 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
     w.Psif = bp.take<float>(blk);
     w.R64 = bp.take<double>(blk);
     w.Y64 = bp.take<double>(blk);
+  } else {
+    w.rb = bp.take<double>(blk);
+    w.dq = bp.take<double>(blk);
+    w.mask = bp.take<double>((size_t)k * k);
   }
   return w;
 }
@@ -307,7 +313,6 @@ struct Deflation {
   double* theta;        // nb (device)
   double* eps;          // shifts of the current columns (device, k)
   double *cA, *cB, *cC, *tmp;  // nb x k small arrays (device)
-  double *rb, *dq;             // N x k: residual and correction of a refinement round
 };
 
 // Extra work of a deflated solve with nocc shifts and nb deflation vectors; pw replaces
@@ -324,8 +329,6 @@ Deflation defl_layout(Bump& bp, const Mesh& m, int k, int nb, double** Ucopy, do
   d.cB = bp.take<double>(64 * 64);
   d.cC = bp.take<double>(64 * 64);
   d.tmp = bp.take<double>(64 * 64);
-  d.rb = bp.take<double>((size_t)m.nf * k);
-  d.dq = bp.take<double>((size_t)m.nf * k);
   *pw = bp.take<double>(project_work_bytes(m.nf, 64, 64) / sizeof(double) + 1);
   return d;
 }
@@ -929,59 +932,71 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
 }
 
 // The FP64 solve and its true residual; reports per-column counts and relative residuals.
+// MINRES stops on its residual estimate in the preconditioner's norm; the result is held to
+// the Euclidean bar ||b - A q|| <= 2 tol ||b|| on every column: columns above it are refined
+// (at most three rounds). maxit bounds the whole solve: the first solve and the refinement
+// rounds draw on one budget, counted in iterations of the slowest column.
 fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k, const double* B,
                       double* Q, double tol, int maxit, int* iters_h, double* relres_h, MRWork& w, Deflation* df,
                       const char* name, hipStream_t s) {
   fe_status st;
   std::vector<double> its, active, rr(k), bb(k);
   bool conv = true;
-  // deflated: a tighter stop test for the first solve, since its residual norm understates
-  // the Euclidean one (by 6 to 17 times on the model molecules)
+  // deflated: a tighter stop test for the first solve, since its residual norm weighs the
+  // deflated directions by 1 / (theta - eps) and so understates the Euclidean one (by 6 to 17
+  // times on the model molecules); refinement below covers what this factor misses
   const double tol1 = df ? tol / 6.0 : tol;
   if ((st = minres_core<double>(m, v, Psi, eps_h, k, B, Q, tol1, maxit, w, its, active, s, df)) != FE_OK) return st;
-  for (int j = 0; j < k; ++j)
+  int used = 0;
+  for (int j = 0; j < k; ++j) {
     if (active[j] > 0.0) conv = false;
-  double* R = df ? df->rb : static_cast<double*>(w.Y);
-  if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, R, w.d1, w.pw, s)) != FE_OK) return st;
+    used = std::max(used, (int)its[j]);
+  }
+  if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
   if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipStreamSynchronize(s));
-  // With a deflated preconditioner MINRES stops on a residual norm that weighs the deflated
-  // directions by 1 / (theta - eps), so the Euclidean residual can be several tol. Refine the
-  // columns above 2 tol: solve (H - eps) d = r for their true residual r, to half of what the
-  // worst of them still needs, and add d (at most three rounds).
-  for (int round = 0; df && conv && round < 3; ++round) {
+  auto above = [&](int j) { return rr[j] > 4.0 * tol * tol * bb[j]; };
+  // Refinement: solve (H - eps) d = r for the true residual r of the columns above 2 tol, to
+  // half of what the worst of them still needs, and add d.
+  for (int round = 0; conv && round < 3; ++round) {
     double need = 1e300;
     std::vector<double> mask((size_t)k * k, 0.0);  // diag(1 for the columns still above 2 tol)
     for (int j = 0; j < k; ++j)
-      if (rr[j] > 4.0 * tol * tol * bb[j]) {
+      if (above(j)) {
         need = std::min(need, std::sqrt(bb[j] / rr[j]));
         mask[(size_t)j * k + j] = 1.0;
       }
     if (need == 1e300) break;
+    if (used >= maxit) break;
     // the other columns get a zero right-hand side: inactive from the start, soon compacted away
-    INVDFT_HIP(hipMemcpyAsync(df->tmp, mask.data(), mask.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    if ((st = rotate(df->rb, k, m.nf, k, df->tmp, k, df->rb, k, s)) != FE_OK) return st;
+    INVDFT_HIP(hipMemcpyAsync(w.mask, mask.data(), mask.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if ((st = rotate(w.rb, k, m.nf, k, w.mask, k, w.rb, k, s)) != FE_OK) return st;
     const double tol2 = std::min(0.5, std::max(1e-14, 0.5 * tol * need));
     std::vector<double> its2, act2;
-    if ((st = minres_core<double>(m, v, Psi, eps_h, k, df->rb, df->dq, tol2, maxit, w, its2, act2, s, df)) != FE_OK)
+    if ((st = minres_core<double>(m, v, Psi, eps_h, k, w.rb, w.dq, tol2, maxit - used, w, its2, act2, s, df)) !=
+        FE_OK)
       return st;
+    int mx = 0;
     for (int j = 0; j < k; ++j) {
       its[j] += its2[j];
+      mx = std::max(mx, (int)its2[j]);
       if (act2[j] > 0.0) conv = false;
     }
-    if ((st = axpby(1.0, df->dq, 1.0, Q, (int64_t)m.nf * k, s)) != FE_OK) return st;
-    if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, df->rb, w.d1, w.pw, s)) != FE_OK) return st;
+    used += mx;
+    if ((st = axpby(1.0, w.dq, 1.0, Q, (int64_t)m.nf * k, s)) != FE_OK) return st;
+    if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
     INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
     INVDFT_HIP(hipStreamSynchronize(s));
   }
   for (int j = 0; j < k; ++j) {
     if (iters_h) iters_h[j] = (int)its[j];
     if (relres_h) relres_h[j] = bb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / bb[j]) : 0.0;
+    if (above(j)) conv = false;
   }
   if (!conv) {
-    std::string msg = std::string(name) + ": some columns did not converge in maxit iterations";
+    std::string msg = std::string(name) + ": some columns did not reach tol (Euclidean residual) in maxit iterations";
     return fail(FE_ENOCONV, msg.c_str());
   }
   return FE_OK;

@@ -105,7 +105,8 @@ __global__ void poisson_finish_kernel(const double* __restrict__ x1, const doubl
   }
 }
 
-// Perdew-Wang 1992, unpolarised: e_c(r_s) and v_c = e_c - (r_s/3) de_c/dr_s
+// Perdew-Wang 1992 correlation of the unpolarised gas (J. P. Perdew and Y. Wang, Phys. Rev. B 45,
+// 13244 (1992), the published parameters of its fit): e_c(r_s) and v_c = e_c - (r_s/3) de_c/dr_s
 __device__ __forceinline__ double pw92_vc(double rho) {
   const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
   const double rs = cbrt(3.0 / (4.0 * kPi * rho));

@@ -62,7 +62,7 @@ def test_adjoint_precisions_match_oracle_gradient(prec):
     rho, B, loss = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d))
     Q, ar = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-10, maxit=20000, prec=prec)
     assert ar.status == 0, ar
-    assert max(ar.relres) <= 5e-10, ar.relres   # stop test is in the preconditioner norm
+    assert max(ar.relres) <= 2e-10, ar.relres   # the Euclidean bar of the solve
     g = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d), Q=Q).cpu().numpy()
     rel = np.linalg.norm(g - ev.grad) / np.linalg.norm(ev.grad)
     assert rel <= 1e-6, rel
@@ -143,7 +143,7 @@ def test_adjoint_column_compaction_matches_oracle(prec):
     rho, B, loss = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d))
     Q, ar = api.adjoint_solve(m, v, Psi, r.eig[:k], B, tol=1e-10, maxit=20000, prec=prec)
     assert ar.status == 0, ar
-    assert max(ar.relres) <= 5e-10, ar.relres   # stop test is in the preconditioner norm
+    assert max(ar.relres) <= 2e-10, ar.relres   # the Euclidean bar of the solve
     assert len(set(ar.iters)) > 1          # columns did converge at different iterations
     g = api.loss_grad(m, Psi, [2.0] * k, _t(rho_d), Q=Q).cpu().numpy()
     rel = np.linalg.norm(g - ev.grad) / np.linalg.norm(ev.grad)

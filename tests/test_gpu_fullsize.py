@@ -154,7 +154,7 @@ def test_adjoint_and_gradient_full_size(cfg):
     Q, ar = api.adjoint_solve(m, v, Psi, eps, B, tol=TOL_ADJ, maxit=20000, prec="f64")
     _say(f"adjoint: max {max(ar.iters)} iterations, max relres {max(ar.relres):.2e}")
     assert ar.status == 0, ar
-    assert max(ar.relres) <= 5 * TOL_ADJ      # stop test is in the preconditioner norm
+    assert max(ar.relres) <= 2 * TOL_ADJ      # the Euclidean bar of the solve
     # q_i orthogonal to every occupied orbital
     assert (Psi.T @ Q).abs().max().item() <= 1e-10 * Q.abs().max().item()
     # true residual of the projected equations with the GPU operator

@@ -117,3 +117,50 @@ def test_lb94_decays_as_minus_one_over_r():
     rho2 = np.logspace(-6, 1, 20)
     assert np.all(xc.lb94_exchange(rho2, 0.3 * rho2) <= xc.slater_exchange(rho2) + 1e-15)
     np.testing.assert_allclose(xc.lb94_exchange(rho2, 0 * rho2), xc.slater_exchange(rho2), rtol=1e-15)
+
+
+# ------------------------------------------------------------- PW92 constants
+# The PW92 fit (Perdew and Wang, Phys. Rev. B 45, 13244 (1992)) is built on the limits of the
+# uniform electron gas, which fix every one of its six constants:
+#   high density  e_c = c0 ln r_s - c1 + O(r_s ln r_s), c0 = (1 - ln 2)/pi^2 (exact), c1 = 0.046644,
+#                 and no r_s^{1/2} term: b1 = e^{-c1/(2 c0)} / (2 c0), b2 = 2 c0 b1^2;
+#   low density   e_c = -d0 / r_s + d1 / r_s^{3/2} + ..., d0 = a1/b4 = 0.4335, d1 = a1 b3 / b4^2 = 1.4408.
+# c1, d0 and d1 are the published expansion coefficients; their printed digits set the tolerances.
+PW92_C1, PW92_D0, PW92_D1 = 0.046644, 0.4335, 1.4408
+
+
+def _pw92_relations(P):
+    """Relative misfit of each defining relation for a parameter set P."""
+    c0 = (1 - np.log(2)) / np.pi ** 2
+    return {
+        "A": (abs(P["A"] / c0 - 1), 2e-5),
+        "b1": (abs(P["b1"] * 2 * P["A"] / np.exp(-PW92_C1 / (2 * P["A"])) - 1), 2e-5),
+        "b2": (abs(P["b2"] / (2 * P["A"] * P["b1"] ** 2) - 1), 2e-5),
+        "d0": (abs(P["a1"] / P["b4"] / PW92_D0 - 1), 2e-4),
+        "d1": (abs(P["a1"] * P["b3"] / P["b4"] ** 2 / PW92_D1 - 1), 1e-4),
+    }
+
+
+def test_pw92_constants_from_electron_gas_limits():
+    for name, (err, tol) in _pw92_relations(xc.PW92).items():
+        assert err < tol, (name, err)
+
+
+def test_pw92_energy_has_both_limits():
+    """The coded e_c (not just its constants) follows both expansions."""
+    rs = np.array([1e-9, 1e-10])
+    lead = xc.pw92_energy(rs) - xc.PW92["A"] * np.log(rs)       # -> -c1 (A itself is pinned above)
+    np.testing.assert_allclose(lead, -PW92_C1, rtol=3e-5)
+    rs = np.array([1e6, 4e6])
+    e = xc.pw92_energy(rs)
+    np.testing.assert_allclose(-e * rs, PW92_D0 - PW92_D1 / np.sqrt(rs), rtol=3e-4)
+
+
+def test_pw92_one_digit_slip_is_caught():
+    """Changing any one constant in its fourth significant digit breaks a relation."""
+    for key in xc.PW92:
+        bad = dict(xc.PW92)
+        v = bad[key]
+        bad[key] = v + 10.0 ** (np.floor(np.log10(abs(v))) - 3)
+        misfit = _pw92_relations(bad)
+        assert any(err >= tol for err, tol in misfit.values()), key
