@@ -367,6 +367,29 @@ fe_status adjoint_along_psi(fe_mesh mesh, const double* Psi, int n, const double
                             double smax, const double* rho, const double* rho_data, double* Q, double* eta_h,
                             double* C_h, void* work, void* stream);
 
+/* ---------------------------------------------------- loss_grad_noalloc --
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): loss_grad with no
+ * work argument. Same arguments, phases, results and errors as loss_grad,
+ * except:
+ *   - phase 1 (Q == NULL) requires rho (the caller's N_f density output);
+ *     loss_grad can keep the density in its work buffer, this call cannot;
+ *   - the scratch (the loss partial sums and the Gram partials of the
+ *     projection of B) is a fixed device array of this library,
+ *     loss_grad_noalloc_max_bytes() bytes (34 MiB), one copy per GPU, held
+ *     until the process ends. A call whose scratch would exceed it returns
+ *     FE_EINVAL (cannot happen for nocc <= 64 on any mesh);
+ *   - the current device must be the one the mesh was created on (FE_EINVAL).
+ * It calls no hipMalloc, hipFree or allocating library routine. Every call on
+ * one GPU uses that GPU's single array: calls that overlap in time on one GPU
+ * (two host threads, or two streams without ordering) race and give wrong
+ * results; calls ordered on one stream are safe. Nothing in the array needs
+ * to start at zero: every partial sum is written before it is read. */
+size_t loss_grad_noalloc_max_bytes(void);
+fe_status loss_grad_noalloc(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc,
+                            const double* rho_data, const double* Q, double tau_bc, double* rho, double* B,
+                            double* grad, double* loss_h, void* stream);
+
 /* --------------------------------------------------------- block helpers --
  * Small FP64 vector kernels used by the host-side L-BFGS driver (Eq. 21):
  * fe_dot returns sum_a x_a y_a over n entries (deterministic reduction);

@@ -44,6 +44,8 @@ SIGNATURES = {
     "adjoint_solve_deflated": (C.c_int, [vp, vp, vp, dp, C.c_int, vp, dp, C.c_int, vp, vp, C.c_double, C.c_int, ip,
                                          dp, vp, vp]),
     "loss_grad": (C.c_int, [vp, vp, dp, C.c_int, vp, vp, C.c_double, vp, vp, vp, dp, vp, vp]),
+    "loss_grad_noalloc": (C.c_int, [vp, vp, dp, C.c_int, vp, vp, C.c_double, vp, vp, vp, dp, vp]),
+    "loss_grad_noalloc_max_bytes": (C.c_size_t, []),
     "fe_dot": (C.c_int, [vp, vp, C.c_int64, dp, vp, vp]),
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),
     "fe_apply_timing": (C.c_int, [C.c_int]),

@@ -512,6 +512,54 @@ fe_status true_residual(const Mesh& m, const double* v, const double* Psi, const
 }
 
 }  // namespace
+
+// Bytes of loss_grad's scratch beyond the density buffer: the loss partials and the
+// projection's Gram partials (what the allocation-free variant holds in its static array).
+size_t loss_grad_scratch_bytes(int64_t nf, int nocc) {
+  Bump bp(nullptr);
+  bp.take<double>(1025);
+  bp.take<char>(project_work_bytes(nf, nocc, nocc));
+  return bp.off;
+}
+
+// Both phases of loss_grad. rho_w: an N_f buffer for the density when rho is NULL (phase 1);
+// scratch: loss_grad_scratch_bytes(nf, nocc) bytes (loss partials, then projection work).
+fe_status loss_grad_impl(const Mesh& m, const double* Psi, const double* occ_h, int nocc, const double* rho_data,
+                         const double* Q, double tau_bc, double* rho, double* B, double* grad, double* loss_h,
+                         double* rho_w, void* scratch, const char* name, hipStream_t s) {
+  fe_status st;
+  Bump bp(scratch);
+  double* lw = bp.take<double>(1025);
+  double* dl = lw + 1024;
+  void* pw = bp.take<char>(project_work_bytes(m.nf, nocc, nocc));
+  if (Q) {
+    if (!grad) return fail(FE_EINVAL, std::string(name) + ": phase 2 needs grad");
+    if (tau_bc > 0 && !rho_data) return fail(FE_EINVAL, std::string(name) + ": tau_bc needs rho_data");
+    if ((st = k_grad(m, Psi, Q, nocc, rho_data, tau_bc, grad, s)) != FE_OK) return st;
+    if (loss_h && rho && rho_data) {
+      if ((st = k_loss(m, rho, rho_data, dl, lw, s)) != FE_OK) return st;
+      INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+      INVDFT_HIP(hipStreamSynchronize(s));
+    }
+    return FE_OK;
+  }
+  if ((B || loss_h) && !rho_data)
+    return fail(FE_EINVAL, std::string(name) + ": rho_data is required for the loss and B");
+  double* r = rho ? rho : rho_w;
+  if (!r) return fail(FE_EINVAL, std::string(name) + ": rho is required");
+  if ((st = k_density(m, Psi, nocc, occ_h, r, s)) != FE_OK) return st;
+  if (B) {
+    if ((st = k_rhs(m, Psi, nocc, occ_h, r, rho_data, B, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, nocc, B, nocc, m.nf, false, pw, s)) != FE_OK) return st;
+  }
+  if (loss_h) {
+    if ((st = k_loss(m, r, rho_data, dl, lw, s)) != FE_OK) return st;
+    INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+    INVDFT_HIP(hipStreamSynchronize(s));
+  }
+  return FE_OK;
+}
+
 }  // namespace invdft
 
 using namespace invdft;
@@ -761,8 +809,7 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
     }
     case FE_OP_LOSS_GRAD:
       bp.take<double>(m.nf);
-      bp.take<double>(1025);
-      bp.take<double>(project_work_bytes(m.nf, nv, nv) / sizeof(double) + 1);
+      bp.take<char>(loss_grad_scratch_bytes(m.nf, nv));
       return bp.off;
     case FE_OP_ALONG_PSI: return along_psi_work_bytes(m.nf, nv);
     case FE_OP_POISSON: return poisson_work_bytes(m.nf);
@@ -892,43 +939,14 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
   if (!Psi || !occ_h) return fail(FE_EINVAL, "loss_grad: Psi and occ_h are required");
   if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "loss_grad: nocc must be in [1, 64]");
   const Mesh& m = mesh->m;
-  hipStream_t s = S(stream);
-  fe_status st;
-  if (Q) {
-    if (!grad) return fail(FE_EINVAL, "loss_grad: phase 2 needs grad");
-    if (tau_bc > 0 && !rho_data) return fail(FE_EINVAL, "loss_grad: tau_bc needs rho_data");
-    if ((st = k_grad(m, Psi, Q, nocc, rho_data, tau_bc, grad, s)) != FE_OK) return st;
-    if (loss_h && rho && rho_data) {
-      if (!work) return fail(FE_EINVAL, "loss_grad: work is NULL");
-      Bump bp(work);
-      bp.take<double>(m.nf);
-      double* lw = bp.take<double>(1025);
-      double* dl = lw + 1024;
-      if ((st = k_loss(m, rho, rho_data, dl, lw, s)) != FE_OK) return st;
-      INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
-      INVDFT_HIP(hipStreamSynchronize(s));
-    }
-    return FE_OK;
-  }
-  if (!work) return fail(FE_EINVAL, "loss_grad: work is NULL");
-  if ((B || loss_h) && !rho_data) return fail(FE_EINVAL, "loss_grad: rho_data is required for the loss and B");
+  const bool needs_work = !Q || (loss_h && rho && rho_data);
+  if (needs_work && !work) return fail(FE_EINVAL, "loss_grad: work is NULL");
+  // work layout: the density buffer (used when rho is NULL), then the scratch
   Bump bp(work);
   double* rho_w = bp.take<double>(m.nf);
-  double* lw = bp.take<double>(1025);
-  void* pw = bp.take<char>(project_work_bytes(m.nf, nocc, nocc));
-  double* r = rho ? rho : rho_w;
-  if ((st = k_density(m, Psi, nocc, occ_h, r, s)) != FE_OK) return st;
-  if (B) {
-    if ((st = k_rhs(m, Psi, nocc, occ_h, r, rho_data, B, s)) != FE_OK) return st;
-    if ((st = project_out(Psi, nocc, B, nocc, m.nf, false, pw, s)) != FE_OK) return st;
-  }
-  if (loss_h) {
-    double* dl = lw + 1024;
-    if ((st = k_loss(m, r, rho_data, dl, lw, s)) != FE_OK) return st;
-    INVDFT_HIP(hipMemcpyAsync(loss_h, dl, sizeof(double), hipMemcpyDeviceToHost, s));
-    INVDFT_HIP(hipStreamSynchronize(s));
-  }
-  return FE_OK;
+  void* scratch = bp.take<char>(loss_grad_scratch_bytes(m.nf, nocc));
+  return loss_grad_impl(m, Psi, occ_h, nocc, rho_data, Q, tau_bc, rho, B, grad, loss_h, work ? rho_w : nullptr,
+                        work ? scratch : nullptr, "loss_grad", S(stream));
 }
 
 // The FP64 solve and its true residual; reports per-column counts and relative residuals.

@@ -127,4 +127,11 @@ fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s);
 fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s);
 
+// loss_grad's two phases (Eqs. 1, 4, 7, 10, 11, 20, 22) over caller-given buffers: rho_w is an
+// N_f density buffer used when rho is NULL; scratch holds loss_grad_scratch_bytes(nf, nocc).
+size_t loss_grad_scratch_bytes(int64_t nf, int nocc);
+fe_status loss_grad_impl(const Mesh& m, const double* Psi, const double* occ_h, int nocc, const double* rho_data,
+                         const double* Q, double tau_bc, double* rho, double* B, double* grad, double* loss_h,
+                         double* rho_w, void* scratch, const char* name, hipStream_t s);
+
 }  // namespace invdft
