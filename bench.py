@@ -3,11 +3,20 @@
 A step is one gradient iteration of the inverse loop: the forward Chebyshev-
 filtered eigensolve (warm-started from the previous iterate's orbitals), the
 density/loss/adjoint right-hand side, the batched MINRES adjoint solve, the
-gradient (all behind the autograd Function), and the potential update. Two
-paths run the same steps to the same tolerances: the plain FP64 GPU path and
-the mixed-precision path (FP32 Chebyshev filter with FP64 Rayleigh-Ritz,
-reductions and adjoint; orbitals recomputed in backward instead of stored).
-`value` is the mixed path's gradient iterations per second.
+gradient (all behind the autograd Function), and the potential update. Three
+paths run the same steps to the same tolerances (every adjoint column held to
+the same Euclidean residual bar):
+  f64    the plain FP64 GPU path (diagonal MINRES preconditioner);
+  f64d   FP64 with the adjoint's preconditioner deflated by the block's buffer
+         Ritz vectors (the same algorithm as the mixed path, in FP64 only);
+  mixed  the mixed-precision path (FP32 Chebyshev filter with FP64
+         Rayleigh-Ritz, reductions and the deflated adjoint; orbitals
+         recomputed in backward instead of stored).
+`value` is the mixed path's gradient iterations per second, timed over --steps
+steps after --warmup; the two comparison paths are timed over
+min(--steps, --compare-steps) steps after min(--warmup, 2), which keeps the
+run to a few minutes (their per-step cost is flat over the loop: the same
+ChFSI pass and MINRES counts step after step).
 
 The roofline object is for the dominant kernel of the timed region, the
 operator apply in the precision that takes the most time: every launch is
@@ -112,7 +121,7 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
     import torch
     prob = inv.InverseProblem(mesh, v_fixed, rho_d, n_elec, X0, opts, vxc=vxc)
     u = prob.zeros_u()
-    losses, grads = [], []
+    losses = []
 
     def one_step(u):
         ur = u.detach().clone().requires_grad_(True)
@@ -124,8 +133,11 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
             api.axpby(-step_len / gmax, g, 1.0, u)
         return float(loss.detach()), g
 
+    g_first = None                      # the gradient at u = 0: the same point on every path
     for w in range(warmup):
         l, g = one_step(u)
+        if g_first is None:
+            g_first = g.clone()
         log(f"  warmup {w}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
     prob.stats = inv.Stats()
     torch.cuda.synchronize()
@@ -134,13 +146,14 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
     for k in range(steps):
         l, g = one_step(u)
         losses.append(l)
-        grads.append(g.clone() if k == 0 else None)
+        if g_first is None:
+            g_first = g.clone()
         log(f"  step {k}: loss {l:.6e}  passes {prob.stats.passes[-1]}  minres {prob.stats.adj_iters[-1]}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     api.apply_timing(False)
     timing = {p: api.apply_timing_read(p) for p in ("f64", "f32")}
-    return elapsed, losses, grads[0], prob, timing
+    return elapsed, losses, g_first, prob, timing
 
 
 def main():
@@ -150,7 +163,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paths", default="f64,mixed")
+    ap.add_argument("--paths", default="mixed,f64,f64d",
+                    help="paths to time; the first is the head path whose rate is `value`")
+    ap.add_argument("--compare-steps", type=int, default=6,
+                    help="timed steps of every path after the first (at most --steps)")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time ks_apply on the workload mesh (used for kernel profiles)")
     ap.add_argument("--reps", type=int, default=20)
@@ -159,8 +175,8 @@ def main():
                     help="mixed path: FP32 filter passes while the largest occupied residual is above this")
     ap.add_argument("--deflate", type=int, default=-1,
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
-                         "path (default: the block's buffer columns; 0: off). The FP64 path always keeps the "
-                         "diagonal preconditioner.")
+                         "and f64d paths (default: the block's buffer columns; 0: off). The f64 path always keeps "
+                         "the diagonal preconditioner.")
     ap.add_argument("--frontend", action="store_true",
                     help="time the Hartree solve and the initial guess on the target density")
     ap.add_argument("--graded", type=float, default=0.0,
@@ -306,31 +322,48 @@ def main():
         common.update(kT=kT, n_states=nconv)
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
+        "f64d": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False,
+                                  deflate=deflate),
         "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=args.switch_tol,
                                    recompute=True, deflate=deflate),
     }
-    for name in args.paths.split(","):
-        log(f"path {name}")
+    order = args.paths.split(",")
+    for k, name in enumerate(order):
+        steps = args.steps if k == 0 else max(1, min(args.steps, args.compare_steps))
+        warm = args.warmup if k == 0 else min(args.warmup, 2)
+        log(f"path {name}: {warm} warmup + {steps} timed steps")
         el, losses, g0, prob, timing = run_path(api, inv, mesh, v_fixed, rho_d, wl.n_elec, Xw, paths[name],
-                                                args.steps, args.warmup, step_len, vxc)
-        results[name] = dict(elapsed=el, losses=losses, g0=g0, stats=prob.stats, timing=timing,
+                                                steps, warm, step_len, vxc)
+        results[name] = dict(elapsed=el, steps=steps, losses=losses, g0=g0, stats=prob.stats, timing=timing,
                              n_incl=prob.state.n)
         for p_, (n_, ms_, b_) in timing.items():
             if n_:
                 log(f"  ks_apply {p_}: {n_} launches, {ms_:.1f} ms, {b_ / ms_ / 1e6:.0f} GB/s")
-        log(f"path {name}: {args.steps / el:.4f} iters/s  forward {prob.stats.t_forward:.2f} s  "
-            f"adjoint {prob.stats.t_adjoint:.2f} s")
+        log(f"path {name}: {steps / el:.4f} iters/s  forward {prob.stats.t_forward / steps:.2f} s/step  "
+            f"adjoint {prob.stats.t_adjoint / steps:.2f} s/step")
         del prob
 
-    head = results.get("mixed") or results["f64"]
+    head_name = order[0]
+    head = results[head_name]
     ips = args.steps / head["elapsed"]
     out_extra = {}
-    if "mixed" in results and "f64" in results:
-        g64, gm = results["f64"]["g0"], results["mixed"]["g0"]
-        rel = float(torch.linalg.vector_norm(gm - g64) / torch.linalg.vector_norm(g64))
-        ips64 = args.steps / results["f64"]["elapsed"]
-        out_extra = {"fp64_path_iters_per_s": ips64, "speedup_vs_fp64_path": ips / ips64,
-                     "grad_rel_diff_mixed_vs_fp64": rel}
+    # every path's first gradient is taken at u = 0 from the same start block: equal accuracy
+    # means these agree to the gradient tolerance
+    for name in order[1:]:
+        r = results[name]
+        ipsx = r["steps"] / r["elapsed"]
+        key = {"f64": "fp64_path", "f64d": "fp64_deflated_path", "mixed": "mixed_path"}[name]
+        out_extra[f"{key}_iters_per_s"] = ipsx
+        out_extra[f"speedup_vs_{key}"] = ips / ipsx
+        gh, gx = head["g0"], r["g0"]
+        out_extra[f"grad_rel_diff_{head_name}_vs_{name}"] = float(
+            torch.linalg.vector_norm(gh - gx) / torch.linalg.vector_norm(gx))
+    out_extra["seconds_per_step"] = {
+        name: {"forward": r["stats"].t_forward / r["steps"], "adjoint": r["stats"].t_adjoint / r["steps"],
+               "total": r["elapsed"] / r["steps"],
+               "chfsi_passes": sum(r["stats"].passes) / max(1, len(r["stats"].passes)),
+               "minres_iters": sum(r["stats"].adj_iters) / max(1, len(r["stats"].adj_iters))}
+        for name, r in results.items()}
 
     # apply alone at the two fixed block widths (context; HIP events on the launch stream)
     ms32, b32 = apply_timing(api, mesh, v_fixed, nv, "f32")
@@ -344,7 +377,7 @@ def main():
     dom = max(tim, key=lambda p: tim[p][1])
     n_l, ms_l, b_l = tim[dom]
     achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
-    traffic = read_traffic(dom, wname, deflate if "mixed" in results else 0)
+    traffic = read_traffic(dom, wname, deflate if head_name in ("mixed", "f64d") else 0)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
@@ -365,7 +398,7 @@ def main():
         t_apply = time.perf_counter() - t0
         del Xc
         # applies per gradient iteration of the measured GPU path: filter passes x degree + MINRES iterations
-        passes = sum(st.passes) / max(1, len(st.passes)) * (st.n_forward / max(1, args.steps))
+        passes = sum(st.passes) / max(1, len(st.passes)) * (st.n_forward / max(1, head["steps"]))
         applies = passes * (wl.cheb_degree + 1) + sum(st.adj_iters) / max(1, len(st.adj_iters)) + 2
         cpu = {"value": 1.0 / (t_apply * applies), "unit": "grad_iter/s", "cores": os.cpu_count(),
                "kind": "oracle",
@@ -384,14 +417,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if "mixed" in results else "f64",
+        "dtype": "f32+f64" if head_name == "mixed" else "f64",
         "data": "synthetic (seeded model molecule; target density from a known potential)",
         "config": {"workload": wname, "p": wl.p, "cells_per_dim": mesh.n, "half_width": wl.half_width,
                    "n_free": mesh.n_free, "electrons": wl.n_elec, "block": nv, "cheb_degree": wl.cheb_degree,
                    **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {}),
                    **({"vxc_h": args.vxc_h, "vxc_vertices": vxc.n_vertices} if vxc is not None else {}),
                    **({"graded_inner_h": args.graded, "growth": 1.35} if args.graded > 0 else {}),
-                   **({"adjoint_deflation": deflate} if "mixed" in results and deflate > 0 else {})},
+                   **({"adjoint_deflation": deflate} if head_name in ("mixed", "f64d") and deflate > 0 else {})},
         "ks_apply_GBps_f32": gbs32,
         "ks_apply_GBps_f64": gbs64,
         "ks_apply_ms_f32": ms32,

@@ -68,6 +68,20 @@ class Workload:
             v -= z / np.sqrt(d2 + self.soft ** 2)
         return v
 
+    def model_density(self, xyz: np.ndarray, width: float = 1.0) -> np.ndarray:
+        """A closed-form molecule-like target density at points xyz: every site carries
+        its charge in electrons as a normalised 3-D Gaussian of standard deviation
+        ``width`` (bohr), so the density is localised at the sites, decays fast and
+        integrates to the electron count over all space. Used where a target that both
+        sides evaluate pointwise is needed instead of the density of a potential."""
+        xyz = np.asarray(xyz, dtype=np.float64)
+        rho = np.zeros(xyz.shape[0])
+        norm = (2.0 * np.pi * width * width) ** -1.5
+        for r0, z in zip(self.sites, self.charges):
+            d2 = np.sum((xyz - r0) ** 2, axis=1)
+            rho += z * norm * np.exp(-d2 / (2.0 * width * width))
+        return rho
+
     def v_xc_target(self, xyz: np.ndarray) -> np.ndarray:
         """The known XC potential v* (sum of Gaussians) at points xyz."""
         xyz = np.asarray(xyz, dtype=np.float64)
