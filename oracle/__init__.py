@@ -21,6 +21,9 @@ finite-element inverse DFT (Sec. 2 and Sec. 3.2):
                 monopole split off in closed form (the Hamiltonian of Sec. 2).
 * ``xcinit``  — the initial guess of Eq. 25 (Slater exchange, PW92 correlation,
                 Fermi-Amaldi tail).
+* ``mapped``  — smoothly mapped hexahedral meshes: the isoparametric geometry, every
+                cell's own dense element stiffness by Gauss quadrature (Eq. 17, Sec. 3.2.3),
+                the lumped mass and the standard-form operator on them (Eq. 19).
 * ``thermal`` — finite temperature: Fermi-Dirac occupancy and mu (Eqs. 4, 5), the
                 adjoint of each degenerate block with Eqs. 8-9 (Sec. 2, Sec. 3.2.2),
                 the gradient of Eq. 10.

@@ -182,6 +182,8 @@ def kinetic_csr(mesh: Mesh3D) -> sp.csr_matrix:
     K = kron(Mc, kron(Mc, K1)) + kron(Mc, kron(K1, Mc)) + kron(K1, kron(Mc, Mc));
     the last Kronecker factor acts on x (x fastest).
     """
+    if hasattr(mesh, "kinetic_csr"):                 # a mesh with its own per-cell matrices
+        return mesh.kinetic_csr()
     m = mesh.m1
     K1 = sp.csr_matrix(m.K1)
     Mc = sp.csr_matrix(m.Mc)
@@ -208,6 +210,8 @@ def kinetic_apply(mesh: Mesh3D, X: np.ndarray) -> np.ndarray:
     X is (N_f, nv), node-major. Each of the three terms of K is applied as three
     1-D products along z, y, x of the W1^{-1/2}-scaled 1-D matrices.
     """
+    if hasattr(mesh, "kinetic_csr"):                 # per-cell matrices: the assembled operator
+        return mesh.kinetic_csr() @ np.asarray(X, dtype=np.float64)
     m = mesh.m1
     n1 = mesh.n1
     s = 1.0 / np.sqrt(m.W1)
@@ -304,6 +308,8 @@ def nodal_gradient(mesh: Mesh3D, f: np.ndarray) -> np.ndarray:
 def kinetic_diag(mesh: Mesh3D) -> np.ndarray:
     """Diagonal of K~/2: the preconditioner of Sec. 3.2.2 (inverse diagonal of the
     kinetic, i.e. negative-Laplacian, part)."""
+    if hasattr(mesh, "kinetic_diag"):
+        return mesh.kinetic_diag()
     m = mesh.m1
     kd = np.diag(m.K1) / m.W1
     md = np.diag(m.Mc) / m.W1
