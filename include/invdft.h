@@ -107,6 +107,22 @@ fe_status fe_mesh_create(int p, int n_cells_per_dim, double half_width, fe_mesh*
  * strictly increasing), FE_ENOMEM, FE_EDEVICE. */
 fe_status fe_mesh_create_graded(int p, int n_cells_per_dim, const double* breaks_h, fe_mesh* out);
 
+/* Mapped mesh (per-cell element matrices: Sec. 3.2.3's batched dense cell products;
+ * the curved, non-tensor cells of adaptive meshes, Sec. 4 and Fig. 6): the uniform
+ * mesh's GLL nodes moved by the smooth map of the box onto itself
+ *   Phi_d(xi) = xi_d + amp (L/pi) sin(pi xi_d / L) sin(pi xi_{d+1} / L), d+1 cyclic,
+ * with isoparametric cells (a cell's shape is the order-p interpolant of its nodes).
+ * Every cell gets its own dense element stiffness (Eq. 17) by Gauss quadrature with
+ * ceil((3p+1)/2) points per axis (exact for linear fields: the patch test), the
+ * overlap is GLL-lumped with |det J| at the nodes (Sec. 3.2.1), and the library
+ * stores K~_e = (1/2) W^{-1/2} K_e W^{-1/2} per cell in FP64 and FP32 (at p = 5:
+ * 14 x 54 x 64 doubles per cell, 387 KB). Same free-node numbering as the uniform
+ * mesh. p in [1, 5], |amp| < 1; FE_EINVAL if the map inverts a cell. Every operator
+ * call accepts the handle; poisson_solve, xc_initial_guess and vxc_mesh_create
+ * return FE_EINVAL for it. Set-up runs on the device (the element matrices on the
+ * FP64 matrix cores) and synchronises the device. */
+fe_status fe_mesh_create_mapped(int p, int n_cells_per_dim, double half_width, double amp, fe_mesh* out);
+
 /* Sizes and the kinetic spectral bound; any output pointer may be NULL. */
 fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h,
                        int* nodes_per_cell_h, double* kin_bound_h);

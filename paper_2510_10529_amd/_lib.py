@@ -28,6 +28,7 @@ i64p = C.POINTER(C.c_int64)
 SIGNATURES = {
     "fe_mesh_create": (C.c_int, [C.c_int, C.c_int, C.c_double, C.POINTER(vp)]),
     "fe_mesh_create_graded": (C.c_int, [C.c_int, C.c_int, dp, C.POINTER(vp)]),
+    "fe_mesh_create_mapped": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(vp)]),
     "fe_mesh_info": (C.c_int, [vp, i64p, i64p, ip, dp]),
     "fe_mesh_nodes": (C.c_int, [vp, vp, vp, vp]),
     "fe_mesh_kinetic_diag": (C.c_int, [vp, vp, vp]),

@@ -44,12 +44,18 @@ def _work(nbytes: int, device):
 class Mesh:
     """Spectral-element mesh of [-L, L]^3 with n^3 cells of order p (device tables)."""
 
-    def __init__(self, p: int, n: int, half_width: float, breaks=None):
+    def __init__(self, p: int, n: int, half_width: float, breaks=None, mapped_amp=None):
         """Uniform cells of 2 half_width / n on [-half_width, half_width]^3, or, with ``breaks``
-        (n + 1 increasing cell boundaries, the same on every axis), the graded mesh they define."""
+        (n + 1 increasing cell boundaries, the same on every axis), the graded mesh they define,
+        or, with ``mapped_amp``, the uniform mesh's nodes moved by the smooth map of the box
+        with that amplitude (curved cells, each with its own dense element matrix)."""
         lib = L.load()
         h = C.c_void_p()
-        if breaks is None:
+        self.mapped_amp = mapped_amp
+        if mapped_amp is not None:
+            L.check(lib.fe_mesh_create_mapped(int(p), int(n), float(half_width), float(mapped_amp), C.byref(h)),
+                    "fe_mesh_create_mapped")
+        elif breaks is None:
             L.check(lib.fe_mesh_create(int(p), int(n), float(half_width), C.byref(h)), "fe_mesh_create")
         else:
             breaks = [float(b) for b in breaks]

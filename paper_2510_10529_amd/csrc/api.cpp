@@ -753,6 +753,30 @@ fe_status fe_mesh_create_graded(int p, int n, const double* breaks_h, fe_mesh* o
   return mesh_create_impl(p, n, 0.0, breaks_h, out);
 }
 
+fe_status fe_mesh_create_mapped(int p, int n, double L, double amp, fe_mesh* out) {
+  if (!out) return fail(FE_EINVAL, "fe_mesh_create_mapped: out is NULL");
+  *out = nullptr;
+  if (p < 1 || p > 5) return fail(FE_EINVAL, "fe_mesh_create_mapped: p must be in [1, 5]");
+  if (!std::isfinite(amp) || std::fabs(amp) >= 1.0)
+    return fail(FE_EINVAL, "fe_mesh_create_mapped: amp must satisfy |amp| < 1");
+  if (n >= 1 && (long long)n * n * n > (1LL << 31) / 64)
+    return fail(FE_EINVAL, "fe_mesh_create_mapped: too many cells");
+  fe_mesh h = nullptr;
+  fe_status st = mesh_create_impl(p, n, L, nullptr, &h);
+  if (st != FE_OK) return st;
+  Mesh& m = h->m;
+  m.mapped = true;
+  m.amp = amp;
+  st = mapped_setup(m, amp);
+  if (st != FE_OK) {
+    const std::string msg = fe_last_error();
+    fe_mesh_destroy(h);
+    return fail(st, msg);
+  }
+  *out = h;
+  return FE_OK;
+}
+
 fe_status fe_mesh_info(fe_mesh mesh, int64_t* n_free_h, int64_t* n_cells_h, int* nodes_per_cell_h,
                        double* kin_bound_h) {
   if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
@@ -786,6 +810,11 @@ fe_status fe_mesh_destroy(fe_mesh mesh) {
   if (m.d_ckap) (void)hipFree(m.d_ckap);
   if (m.d_cgl) (void)hipFree(m.d_cgl);
   if (m.d_cgr) (void)hipFree(m.d_cgr);
+  if (m.d_wn) (void)hipFree(m.d_wn);
+  if (m.d_kdn) (void)hipFree(m.d_kdn);
+  if (m.d_xyz) (void)hipFree(m.d_xyz);
+  if (m.d_Ke64) (void)hipFree(m.d_Ke64);
+  if (m.d_Ke32) (void)hipFree(m.d_Ke32);
   delete mesh;
   return FE_OK;
 }

@@ -1028,7 +1028,8 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
   // algorithmic bytes: X read, Y written, Z read when given (the Chebyshev term), v read
   const double blocks = a.Z ? 3.0 : 2.0;
   TimedLaunch t{g_timing.take(), g_timing.take(), (int)prec,
-                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0)};
+                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0) +
+                    (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0)};
   if (!t.start || !t.stop) return fail(FE_EDEVICE, "ks_apply timing: hipEventCreate failed");
   INVDFT_HIP(hipEventRecord(t.start, s));
   const fe_status st = launch_apply_untimed(m, a, prec, s);
@@ -1038,6 +1039,7 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
 }
 
 static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s) {
+  if (m.mapped) return m.nf == 0 ? FE_OK : launch_apply_mapped(m, a, prec, s);
   KParams prm;
   std::memset(&prm, 0, sizeof(prm));
   prm.X = a.X;

@@ -206,6 +206,7 @@ extern "C" fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma
   const Mesh* mp = mesh_tables(mesh);
   if (!mp) return fail(FE_EINVAL, "mesh handle is NULL");
   if (!rho || !phi || !work) return fail(FE_EINVAL, "poisson_solve: NULL argument");
+  if (mp->mapped) return fail(FE_EINVAL, "poisson_solve: mapped meshes are not supported");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "poisson_solve: tol > 0 and maxit >= 1 required");
   if (!(sigma >= 0.0)) return fail(FE_EINVAL, "poisson_solve: sigma must be >= 0");
   const Mesh& m = *mp;
@@ -301,6 +302,7 @@ extern "C" fe_status xc_initial_guess(fe_mesh mesh, const double* rho, const dou
   const Mesh* mp = mesh_tables(mesh);
   if (!mp) return fail(FE_EINVAL, "mesh handle is NULL");
   if (!rho || !v_h || !v) return fail(FE_EINVAL, "xc_initial_guess: NULL argument");
+  if (mp->mapped) return fail(FE_EINVAL, "xc_initial_guess: mapped meshes are not supported");
   if (!(n_elec > 0.0) || !(tau > 0.0)) return fail(FE_EINVAL, "xc_initial_guess: n_elec > 0 and tau > 0 required");
   if (exchange != FE_XC_SLATER && exchange != FE_XC_LB94) return fail(FE_EINVAL, "xc_initial_guess: unknown exchange");
   if (exchange == FE_XC_LB94 && !work) return fail(FE_EINVAL, "xc_initial_guess: LB94 needs work");

@@ -40,6 +40,17 @@ struct Mesh {
   double* d_ckap = nullptr;
   double* d_cgl = nullptr;
   double* d_cgr = nullptr;
+  // mapped meshes (cells curved by a smooth map of the box; every cell its own dense
+  // matrix): per free node W, diag(K~/2) and coordinates, and the per-cell scaled matrices
+  // in MFMA fragment order (map_mt 16-row tiles x map_ks 4-column steps x 64 per cell)
+  bool mapped = false;
+  double amp = 0.0;
+  int map_mt = 0, map_ks = 0;
+  double* d_wn = nullptr;
+  double* d_kdn = nullptr;
+  double* d_xyz = nullptr;
+  double* d_Ke64 = nullptr;
+  float* d_Ke32 = nullptr;
 };
 
 // the tables behind a mesh handle (NULL for a NULL handle)
@@ -78,6 +89,11 @@ struct ApplyArgs {
   const double* d_colscale;   // device array (nv) or nullptr: output column j scaled by it
 };
 fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
+// mapped meshes: per-cell matrices and node tables (m.mapped set, m.nf etc. filled), the apply,
+// and the bytes of one precision's matrices
+fe_status mapped_setup(Mesh& m, double amp);
+fe_status launch_apply_mapped(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
+size_t mapped_matrix_bytes(const Mesh& m, fe_prec prec);
 fe_status apply_timing(int enable);
 fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes);
 

@@ -25,27 +25,31 @@ __device__ __forceinline__ void node_xyz(long long a, int n1, int* ix, int* iy, 
   *iz = (int)(r / n1l);
 }
 
-__global__ void nodes_kernel(const double* __restrict__ x1, const double* __restrict__ w1, int n1, long long nf,
-                             double* __restrict__ xyz, double* __restrict__ w) {
+// wn, xyzn: per-node tables of a mapped mesh (NULL: products of the 1-D tables)
+__global__ void nodes_kernel(const double* __restrict__ x1, const double* __restrict__ w1, const double* __restrict__ wn,
+                             const double* __restrict__ xyzn, int n1, long long nf, double* __restrict__ xyz,
+                             double* __restrict__ w) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
     int ix, iy, iz;
     node_xyz(a, n1, &ix, &iy, &iz);
     if (xyz) {
-      xyz[3 * a + 0] = x1[ix];
-      xyz[3 * a + 1] = x1[iy];
-      xyz[3 * a + 2] = x1[iz];
+      xyz[3 * a + 0] = xyzn ? xyzn[3 * a + 0] : x1[ix];
+      xyz[3 * a + 1] = xyzn ? xyzn[3 * a + 1] : x1[iy];
+      xyz[3 * a + 2] = xyzn ? xyzn[3 * a + 2] : x1[iz];
     }
-    if (w) w[a] = w1[ix] * w1[iy] * w1[iz];
+    if (w) w[a] = wn ? wn[a] : w1[ix] * w1[iy] * w1[iz];
   }
 }
 
 // diag(K~/2)_a = (kd(x) md(y) md(z) + md(x) kd(y) md(z) + md(x) md(y) kd(z)) / 2
-__global__ void kdiag_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
-                             double* __restrict__ d) {
+// (kdn: the per-node diagonal of a mapped mesh, or NULL)
+__global__ void kdiag_kernel(const double* __restrict__ kd1, const double* __restrict__ md1,
+                             const double* __restrict__ kdn, int n1, long long nf, double* __restrict__ d) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
     int ix, iy, iz;
     node_xyz(a, n1, &ix, &iy, &iz);
-    d[a] = 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
+    d[a] = kdn ? kdn[a]
+               : 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
   }
 }
 
@@ -55,21 +59,21 @@ struct Occ {
 
 // rho_a = sum_i f_i psi_{a,i}^2 / W_a   (Eq. 4)
 __global__ void density_kernel(const double* __restrict__ Psi, int nocc, Occ occ, const double* __restrict__ w1,
-                               int n1, long long nf, double* __restrict__ rho) {
+                               const double* __restrict__ wn, int n1, long long nf, double* __restrict__ rho) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
     int ix, iy, iz;
     node_xyz(a, n1, &ix, &iy, &iz);
     const double* row = Psi + a * nocc;
     double s = 0.0;
     for (int i = 0; i < nocc; ++i) s += occ.f[i] * row[i] * row[i];
-    rho[a] = s / (w1[ix] * w1[iy] * w1[iz]);
+    rho[a] = s / (wn ? wn[a] : w1[ix] * w1[iy] * w1[iz]);
   }
 }
 
 // partial sums of W_a (rho_data,a - rho_a)^2   (Eq. 1, w = 1)
 __global__ void loss_partial_kernel(const double* __restrict__ rho, const double* __restrict__ rho_d,
-                                    const double* __restrict__ w1, int n1, long long nf, long long per,
-                                    double* __restrict__ partial) {
+                                    const double* __restrict__ w1, const double* __restrict__ wn, int n1,
+                                    long long nf, long long per, double* __restrict__ partial) {
   __shared__ double red[256];
   const long long b0 = (long long)blockIdx.x * per;
   const long long b1 = min(nf, b0 + per);
@@ -78,7 +82,7 @@ __global__ void loss_partial_kernel(const double* __restrict__ rho, const double
     int ix, iy, iz;
     node_xyz(a, n1, &ix, &iy, &iz);
     const double d = rho_d[a] - rho[a];
-    s += w1[ix] * w1[iy] * w1[iz] * d * d;
+    s += (wn ? wn[a] : w1[ix] * w1[iy] * w1[iz]) * d * d;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -275,12 +279,13 @@ __global__ void defl_scale_kernel(const double* __restrict__ c, const double* __
   }
 }
 
-__global__ void dinv_kernel(const double* __restrict__ kd1, const double* __restrict__ md1, int n1, long long nf,
-                            double* __restrict__ dinv) {
+__global__ void dinv_kernel(const double* __restrict__ kd1, const double* __restrict__ md1,
+                            const double* __restrict__ kdn, int n1, long long nf, double* __restrict__ dinv) {
   for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < nf; a += (long long)gridDim.x * blockDim.x) {
     int ix, iy, iz;
     node_xyz(a, n1, &ix, &iy, &iz);
-    const double d = 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
+    const double d =
+        kdn ? kdn[a] : 0.5 * (kd1[ix] * md1[iy] * md1[iz] + md1[ix] * kd1[iy] * md1[iz] + md1[ix] * md1[iy] * kd1[iz]);
     dinv[a] = 1.0 / d;
   }
 }
@@ -341,19 +346,22 @@ __global__ void sub_from_kernel(const double* __restrict__ b, double* __restrict
 }  // namespace
 
 fe_status k_nodes(const Mesh& m, double* xyz, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(nodes_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.n1, (long long)m.nf, xyz, w);
+  hipLaunchKernelGGL(nodes_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.d_wn, m.d_xyz, m.n1,
+                     (long long)m.nf, xyz, w);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
 fe_status k_kdiag(const Mesh& m, double* d, hipStream_t s) {
-  hipLaunchKernelGGL(kdiag_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.n1, (long long)m.nf, d);
+  hipLaunchKernelGGL(kdiag_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.d_kdn, m.n1,
+                     (long long)m.nf, d);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
 fe_status k_dinv(const Mesh& m, double* dinv, hipStream_t s) {
-  hipLaunchKernelGGL(dinv_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.n1, (long long)m.nf, dinv);
+  hipLaunchKernelGGL(dinv_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, m.d_kd1, m.d_md1, m.d_kdn, m.n1,
+                     (long long)m.nf, dinv);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -361,7 +369,7 @@ fe_status k_dinv(const Mesh& m, double* dinv, hipStream_t s) {
 fe_status k_density(const Mesh& m, const double* Psi, int nocc, const double* occ_h, double* rho, hipStream_t s) {
   Occ o{};
   for (int i = 0; i < nocc; ++i) o.f[i] = occ_h[i];
-  hipLaunchKernelGGL(density_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, Psi, nocc, o, m.d_w1, m.n1,
+  hipLaunchKernelGGL(density_kernel, dim3(grid_for(m.nf)), dim3(256), 0, s, Psi, nocc, o, m.d_w1, m.d_wn, m.n1,
                      (long long)m.nf, rho);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
@@ -373,7 +381,7 @@ fe_status k_loss(const Mesh& m, const double* rho, const double* rho_d, double* 
   const int nblk = (int)std::max<long long>(1, std::min<long long>((m.nf + 4095) / 4096, 1024));
   const long long per = (m.nf + nblk - 1) / nblk;
   double* partial = static_cast<double*>(work);
-  hipLaunchKernelGGL(loss_partial_kernel, dim3(nblk), dim3(256), 0, s, rho, rho_d, m.d_w1, m.n1, (long long)m.nf,
+  hipLaunchKernelGGL(loss_partial_kernel, dim3(nblk), dim3(256), 0, s, rho, rho_d, m.d_w1, m.d_wn, m.n1, (long long)m.nf,
                      per, partial);
   INVDFT_HIP(hipGetLastError());
   hipLaunchKernelGGL(sum_serial_kernel, dim3(1), dim3(64), 0, s, partial, nblk, out);

@@ -163,6 +163,7 @@ extern "C" fe_status vxc_mesh_create(fe_mesh mesh, int mx, const double* tx_h, i
   const Mesh* m = mesh_tables(mesh);
   if (!m || !out) return fail(FE_EINVAL, "vxc_mesh_create: mesh and out are required");
   *out = nullptr;
+  if (m->mapped) return fail(FE_EINVAL, "vxc_mesh_create: mapped orbital meshes are not supported");
   const int ms[3] = {mx, my, mz};
   const double* ts[3] = {tx_h, ty_h, tz_h};
   for (int d = 0; d < 3; ++d) {
