@@ -44,6 +44,13 @@ bohr on the inner cube [-L/2, L/2]^3, growing by 1.35 towards the box (for workl
 and H = 0.6: 36 cells per axis, 5.7 M free nodes, against 40 cells of 0.8 bohr and
 7.9 M nodes for the uniform mesh).
 
+With --mapped A the orbitals live on the mapped mesh of amplitude A (the workload's uniform
+mesh with its nodes moved by a smooth map of the box: curved cells, every cell its own dense
+element matrix, applied as batched MFMA cell products with gather and scatter, Sec. 3.2.3).
+The roofline then covers that apply, whose algorithmic bytes include the per-cell matrices;
+it is bound by HBM while its arithmetic intensity is below the FP64 ridge and by the FP64
+matrix cores above it.
+
 With --frontend the set-up also times the physics front end on the target density: the
 Hartree potential by the finite-element Poisson solve and the initial guess of Eq. 25
 (LB94 exchange + PW92 correlation, Fermi-Amaldi tail).
@@ -63,6 +70,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_TFLOPS = 78.6
 
 
 def log(msg):
@@ -88,8 +96,30 @@ def apply_timing(api, mesh, v, nv, prec, reps=20):
     ms = e0.elapsed_time(e1) / reps
     s = 8 if prec == "f64" else 4
     algo_bytes = 2 * mesh.n_free * nv * s + mesh.n_free * 8
+    if getattr(mesh, "mapped_amp", None) is not None:   # the per-cell matrices stream once per apply
+        npc = mesh.nodes_per_cell
+        algo_bytes += mesh.n_cells * ((npc + 15) // 16) * ((npc + 3) // 4) * 64 * s
     del X, Y
     return ms, algo_bytes
+
+
+def host_cpu():
+    """(CPU model, BLAS threads the oracle's dense products use) of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or threads
+    except Exception:
+        pass
+    return model, threads
 
 
 def kernel_source_hash():
@@ -152,7 +182,7 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     api.apply_timing(False)
-    timing = {p: api.apply_timing_read(p) for p in ("f64", "f32")}
+    timing = {p: api.apply_timing_read(p) for p in ("f64", "f32")}      # (launches, ms, bytes, columns)
     return elapsed, losses, g_first, prob, timing
 
 
@@ -181,6 +211,8 @@ def main():
                     help="time the Hartree solve and the initial guess on the target density")
     ap.add_argument("--graded", type=float, default=0.0,
                     help="inner cell size of a graded orbital mesh (0: the workload's uniform mesh)")
+    ap.add_argument("--mapped", type=float, default=None,
+                    help="amplitude of the smooth map of a mapped orbital mesh (per-cell dense matrices)")
     ap.add_argument("--vxc-h", type=float, default=0.0,
                     help="cell size of the linear XC mesh on the inner cube (0: nodal XC potential)")
     args = ap.parse_args()
@@ -201,7 +233,10 @@ def main():
     wl = workload(args.config)
     log(f"workload {wl.name}: p={wl.p} n={wl.n} L={wl.half_width} N_e={wl.n_elec}")
     breaks = vxc_vertices(wl.half_width, args.graded, 0.5 * wl.half_width, 1.35) if args.graded > 0 else None
-    mesh = api.Mesh(wl.p, wl.n, wl.half_width, breaks=breaks)
+    if args.mapped is not None and (breaks is not None or args.vxc_h > 0 or args.frontend):
+        print("--mapped does not combine with --graded, --vxc-h or --frontend", file=sys.stderr)
+        sys.exit(2)
+    mesh = api.Mesh(wl.p, wl.n, wl.half_width, breaks=breaks, mapped_amp=args.mapped)
     xyz, W = mesh.nodes()
     xyz_h = xyz.cpu().numpy()
     del xyz
@@ -217,6 +252,8 @@ def main():
     wname = wl.name if kT <= 0 else f"{wl.name}-kT{kT:g}"
     if args.graded > 0:
         wname += f"-graded{args.graded:g}"
+    if args.mapped is not None:
+        wname += f"-mapped{args.mapped:g}"
     if args.vxc_h > 0:
         wname += f"-vxc{args.vxc_h:g}"
     log(f"N_f={mesh.n_free} nocc={nocc} nv={nv}" + (f" kT={kT} converged={nconv}" if kT > 0 else ""))
@@ -336,7 +373,7 @@ def main():
                                                 steps, warm, step_len, vxc)
         results[name] = dict(elapsed=el, steps=steps, losses=losses, g0=g0, stats=prob.stats, timing=timing,
                              n_incl=prob.state.n)
-        for p_, (n_, ms_, b_) in timing.items():
+        for p_, (n_, ms_, b_, _c) in timing.items():
             if n_:
                 log(f"  ks_apply {p_}: {n_} launches, {ms_:.1f} ms, {b_ / ms_ / 1e6:.0f} GB/s")
         log(f"path {name}: {steps / el:.4f} iters/s  forward {prob.stats.t_forward / steps:.2f} s/step  "
@@ -375,36 +412,73 @@ def main():
     # dominant kernel of the head path's timed steps: the apply precision with the most time
     tim = head["timing"]
     dom = max(tim, key=lambda p: tim[p][1])
-    n_l, ms_l, b_l = tim[dom]
+    n_l, ms_l, b_l, c_l = tim[dom]
     achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
     traffic = read_traffic(dom, wname, deflate if head_name in ("mixed", "f64d") else 0)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
                 "algorithmic_bytes_per_launch": b_l / n_l}
+    if args.mapped is not None:
+        # dense cell products: 2 n_c n_p^2 flops per column of each launch
+        s_b = 8 if dom == "f64" else 4
+        kb = mesh.n_cells * ((mesh.nodes_per_cell + 15) // 16) * ((mesh.nodes_per_cell + 3) // 4) * 64 * s_b
+        nv_mean = c_l / n_l
+        flops = 2.0 * mesh.n_cells * mesh.nodes_per_cell ** 2 * nv_mean
+        ai = flops / (b_l / n_l)
+        roofline.update({"kernel": f"ks_apply_mapped_{dom}", "arithmetic_intensity": ai,
+                         "mean_columns": nv_mean, "matrix_bytes_per_launch": kb})
+        if ai > FP64_MFMA_TFLOPS * 1e3 / HBM_PEAK_GBS:
+            tf = flops / (ms_l / n_l) / 1e9
+            roofline.update({"bound": "mfma", "achieved": tf, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tf / FP64_MFMA_TFLOPS})
     st = head["stats"]
     applies = None
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import fe as ofe
-        log("cpu baseline: one oracle Kronecker apply of the orbital block on the full mesh")
-        om = ofe.mesh3d(wl.p, wl.n, wl.half_width) if breaks is None else ofe.mesh3d_graded(wl.p, breaks)
         rng = np.random.default_rng(5)
         ncol = head["n_incl"]                      # the orbital block the head path carries
-        Xc = rng.standard_normal((om.n_free, ncol))
-        vc = v_fixed.cpu().numpy()
-        t0 = time.perf_counter()
-        ofe.hamiltonian_apply(om, vc, Xc)
-        t_apply = time.perf_counter() - t0
+        if args.mapped is None:
+            log("cpu baseline: one oracle Kronecker apply of the orbital block on the full mesh")
+            om = ofe.mesh3d(wl.p, wl.n, wl.half_width) if breaks is None else ofe.mesh3d_graded(wl.p, breaks)
+            Xc = rng.standard_normal((om.n_free, ncol))
+            vc = v_fixed.cpu().numpy()
+            t0 = time.perf_counter()
+            ofe.hamiltonian_apply(om, vc, Xc)
+            t_apply = time.perf_counter() - t0
+            what = f"one FP64 oracle Kronecker apply of the {ncol}-column block on the {om.n_free}-node mesh"
+        else:
+            # the oracle's assembled operator on a 4^3-cell mapped mesh of the same order and cell
+            # size, timed per cell and scaled to the workload's cell count
+            from oracle import mapped as omapped
+            nsm = 4
+            om = omapped.mapped_mesh(wl.p, nsm, wl.half_width * nsm / wl.n, args.mapped)
+            Xc = rng.standard_normal((om.n_free, ncol))
+            vc = rng.uniform(-1, 1, om.n_free)
+            Kc = om.kinetic_csr()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                Kc @ Xc + vc[:, None] * Xc
+            t_apply = (time.perf_counter() - t0) / 5 * mesh.n_cells / nsm ** 3
+            what = (f"the oracle's assembled FP64 operator on a {nsm}^3-cell mapped mesh ({om.n_free} nodes, "
+                    f"{ncol} columns), scaled by cells to the {mesh.n_cells}-cell mesh")
         del Xc
         # applies per gradient iteration of the measured GPU path: filter passes x degree + MINRES iterations
         passes = sum(st.passes) / max(1, len(st.passes)) * (st.n_forward / max(1, head["steps"]))
         applies = passes * (wl.cheb_degree + 1) + sum(st.adj_iters) / max(1, len(st.adj_iters)) + 2
-        cpu = {"value": 1.0 / (t_apply * applies), "unit": "grad_iter/s", "cores": os.cpu_count(),
-               "kind": "oracle",
-               "sample": (f"one FP64 oracle Kronecker apply of the {ncol}-column block on the {om.n_free}-node "
-                          f"mesh ({t_apply:.1f} s), scaled by {applies:.0f} applies per gradient iteration "
+        model, threads = host_cpu()
+        cpu = {"value": 1.0 / (t_apply * applies), "unit": "grad_iter/s", "cores": threads,
+               "kind": "oracle", "cpu_model": model, "logical_cpus": os.cpu_count(),
+               "sample": (f"{what} ({t_apply:.1f} s), scaled by {applies:.0f} applies per gradient iteration "
                           f"(the GPU path's measured filter passes x degree + MINRES iterations)")}
+        gpath = os.path.join(ROOT, "tests", "golden", "mol10_q4_24.json")
+        if os.path.exists(gpath):            # the oracle's own method, timed where the fixture was written
+            g = json.load(open(gpath))
+            cpu["oracle_full_method"] = {"workload": g["workload"], "n_free": g["n_free"],
+                                         "seconds_per_gradient_iteration": g["oracle_seconds"]["gradient_iteration"],
+                                         "method": "eigsh (tol 1e-13) + projected CG (rtol 1e-12)",
+                                         "host": g["host"]}
 
     line = {
         "metric": "ks_apply GB/s (% roofline) + inverse-DFT gradient iters/s vs FP64 GPU path",
@@ -424,6 +498,7 @@ def main():
                    **({"kT": kT, "converged": nconv, "orbitals_included": head["n_incl"]} if kT > 0 else {}),
                    **({"vxc_h": args.vxc_h, "vxc_vertices": vxc.n_vertices} if vxc is not None else {}),
                    **({"graded_inner_h": args.graded, "growth": 1.35} if args.graded > 0 else {}),
+                   **({"mapped_amp": args.mapped, "cells": mesh.n_cells} if args.mapped is not None else {}),
                    **({"adjoint_deflation": deflate} if head_name in ("mixed", "f64d") and deflate > 0 else {})},
         "ks_apply_GBps_f32": gbs32,
         "ks_apply_GBps_f64": gbs64,

@@ -422,13 +422,16 @@ fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_
  * fe_apply_timing(enable): 1 starts a new measurement (clears the record),
  *   0 stops recording (the record is kept). Host-side, process-wide; not
  *   thread-safe while launches are in flight.
- * fe_apply_timing_read(prec, launches, ms, bytes): waits for the recorded
- *   events and returns, for launches in precision prec (FE_F64 or FE_F32),
- *   their count, summed duration in milliseconds and summed algorithmic
- *   bytes (2 N_f nv s + 8 N_f per launch, s = 8 or 4). Any output may be NULL.
+ * fe_apply_timing_read(prec, launches, ms, bytes, columns): waits for the
+ *   recorded events and returns, for launches in precision prec (FE_F64 or
+ *   FE_F32), their count, summed duration in milliseconds, summed algorithmic
+ *   bytes (X read, Y written, Z read when the Chebyshev term is present, v read:
+ *   (2 or 3) N_f nv s + 8 N_f per launch, s = 8 or 4; on a mapped mesh also the
+ *   per-cell matrices of that precision) and summed column counts nv. Any
+ *   output may be NULL.
  * Errors: FE_EINVAL for another prec, FE_EDEVICE for a failed event call. */
 fe_status fe_apply_timing(int enable);
-fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes);
+fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns);
 
 #ifdef __cplusplus
 }

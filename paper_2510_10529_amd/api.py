@@ -287,10 +287,13 @@ def apply_timing(enable: bool):
 
 
 def apply_timing_read(prec: str = "f64"):
-    """(launches, total ms, total algorithmic bytes) of the recorded applies in precision prec."""
+    """(launches, total ms, total algorithmic bytes, total columns) of the recorded applies in
+    precision prec."""
     n, ms, b = C.c_int64(), C.c_double(), C.c_double()
-    L.check(L.load().fe_apply_timing_read(PREC[prec], C.byref(n), C.byref(ms), C.byref(b)), "fe_apply_timing_read")
-    return n.value, ms.value, b.value
+    cols = C.c_double()
+    L.check(L.load().fe_apply_timing_read(PREC[prec], C.byref(n), C.byref(ms), C.byref(b), C.byref(cols)),
+            "fe_apply_timing_read")
+    return n.value, ms.value, b.value, cols.value
 
 
 @dataclass

@@ -1188,8 +1188,8 @@ fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_
 
 fe_status fe_apply_timing(int enable) { return apply_timing(enable); }
 
-fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes) {
-  return apply_timing_read(prec, launches, ms, bytes);
+fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns) {
+  return apply_timing_read(prec, launches, ms, bytes, columns);
 }
 
 }  // extern "C"

@@ -970,6 +970,7 @@ struct TimedLaunch {
   hipEvent_t start, stop;
   int prec;
   double bytes;
+  double cols;
 };
 struct ApplyTiming {
   bool on = false;
@@ -1002,10 +1003,10 @@ fe_status apply_timing(int enable) {
   return FE_OK;
 }
 
-fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes) {
+fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns) {
   if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "fe_apply_timing_read: prec must be FE_F64 or FE_F32");
   int64_t n = 0;
-  double t = 0.0, b = 0.0;
+  double t = 0.0, b = 0.0, cl = 0.0;
   for (auto& r : g_timing.rec) {
     if (r.prec != (int)prec) continue;
     INVDFT_HIP(hipEventSynchronize(r.stop));
@@ -1014,10 +1015,12 @@ fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double*
     ++n;
     t += e;
     b += r.bytes;
+    cl += r.cols;
   }
   if (launches) *launches = n;
   if (ms) *ms = t;
   if (bytes) *bytes = b;
+  if (columns) *columns = cl;
   return FE_OK;
 }
 
@@ -1029,7 +1032,8 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
   const double blocks = a.Z ? 3.0 : 2.0;
   TimedLaunch t{g_timing.take(), g_timing.take(), (int)prec,
                 (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0) +
-                    (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0)};
+                    (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0),
+                (double)a.nv};
   if (!t.start || !t.stop) return fail(FE_EDEVICE, "ks_apply timing: hipEventCreate failed");
   INVDFT_HIP(hipEventRecord(t.start, s));
   const fe_status st = launch_apply_untimed(m, a, prec, s);

@@ -95,7 +95,7 @@ fe_status mapped_setup(Mesh& m, double amp);
 fe_status launch_apply_mapped(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
 size_t mapped_matrix_bytes(const Mesh& m, fe_prec prec);
 fe_status apply_timing(int enable);
-fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes);
+fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns);
 
 // Block operations (FP64 reductions; T = double or float storage).
 // Gram: out (nx x ny, row-major, FP64 device) = X^T Y over the first N rows.

@@ -25,9 +25,10 @@
 // (the diagonal and the Chebyshev term) and eight launches of cell products, one per
 // parity class (ex, ey, ez mod 2): cells of one class share no node, so each launch adds
 // its contributions with plain read-modify-write, in a fixed order, bitwise reproducibly.
-// A workgroup gathers a cell's X_e (n_p x 16 or 32 columns) into LDS, and each wavefront
-// streams its M-tiles of K~_e from HBM through v_mfma_f64_16x16x4f64 (FP32 storage is
-// widened to FP64 in registers: the product is bound by the matrix stream, not the MFMA).
+// A workgroup gathers a cell's X_e (n_p x up to 64 columns) into LDS, and each wavefront
+// streams its M-tiles of K~_e from HBM through v_mfma_f64_16x16x4f64, all its tiles at once
+// (FP32 storage is widened to FP64 in registers). Up to 64 columns the matrices stream once
+// per apply; the product is HBM-bound up to about 32 FP64 columns and FP64-MFMA-bound beyond.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -337,13 +338,23 @@ __global__ void mapped_diag_kernel(const MapApply a, long long nf) {
   }
 }
 
-// One parity class: workgroup = (cell of the class, chunk of JC columns).
-template <typename T, int P, int JC>
-__global__ __launch_bounds__(kMapThreads) void mapped_cell_kernel(const MapApply a) {
+// One parity class: workgroup = (cell of the class, chunk of 16 NTL columns). Wavefront w
+// owns the M-tiles w, w + 4, ... (MTI of them) and keeps MTI x NTL independent accumulators,
+// so consecutive MFMAs never wait on each other and every fragment of K~_e loaded from HBM
+// feeds NTL products. The gathered block lives in LDS in the storage precision (LT).
+template <typename T, int P, int NTL, int NT>
+__global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
   constexpr int P1 = P + 1, NP = P1 * P1 * P1;
   constexpr int NP4 = (NP + 3) / 4 * 4;
-  constexpr int NTL = JC / 16;
-  __shared__ double sX[NP4][JC];
+  constexpr int JC = 16 * NTL;
+  constexpr int MT = (NP + 15) / 16, KS = NP4 / 4;
+  constexpr int NW = NT / 64;
+  constexpr int MTI = (MT + NW - 1) / NW;
+  constexpr int EV = 16 / sizeof(T);          // elements per 16-byte load
+  // a B fragment reads 16 columns of 4 consecutive rows: a row pitch of 16 (mod 32) elements
+  // puts the four rows on different LDS banks (FP32) or bank halves (FP64)
+  constexpr int JP = JC + ((JC == 32 || (JC == 64 && sizeof(T) == 4)) ? 16 : 0);
+  __shared__ __attribute__((aligned(16))) T sX[NP4][JP];
   __shared__ long long sNode[NP4];   // free-node index of each local node, -1 at Dirichlet nodes
   const T* X = static_cast<const T*>(a.X);
   T* Y = static_cast<T*>(a.Y);
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(kMapThreads) void mapped_cell_kernel(const MapApply
   const int ex = a.cx + 2 * (c % a.ncx), ey = a.cy + 2 * ((c / a.ncx) % a.ncy), ez = a.cz + 2 * (c / (a.ncx * a.ncy));
   const int j0 = jc * JC;
   const int pn = P * a.n;
-  for (int l = tid; l < NP4; l += kMapThreads) {
+  for (int l = tid; l < NP4; l += NT) {
     long long idx = -1;
     if (l < NP) {
       const int gx = ex * P + l % P1, gy = ey * P + (l / P1) % P1, gz = ez * P + l / (P1 * P1);
@@ -364,27 +375,58 @@ __global__ __launch_bounds__(kMapThreads) void mapped_cell_kernel(const MapApply
     sNode[l] = idx;
   }
   __syncthreads();
-  for (int e = tid; e < NP4 * JC; e += kMapThreads) {
-    const int l = e / JC, jj = e % JC;
+  // gather X_e: 16-byte pieces where the row pitch keeps them aligned and inside the block
+  typedef T TV __attribute__((ext_vector_type(EV)));
+  const bool vec = (a.ld % EV) == 0;
+  for (int e = tid; e < NP4 * (JC / EV); e += NT) {
+    const int l = e / (JC / EV), jj = (e % (JC / EV)) * EV;
     const long long node = sNode[l];
     const int j = j0 + jj;
-    sX[l][jj] = (node >= 0 && j < a.nv) ? (double)X[(size_t)node * a.ld + j] : 0.0;
+    TV val;
+    if (node >= 0 && vec && j + EV <= a.nv) {
+      val = *reinterpret_cast<const TV*>(X + (size_t)node * a.ld + j);
+    } else {
+#pragma unroll
+      for (int q = 0; q < EV; ++q) val[q] = (node >= 0 && j + q < a.nv) ? X[(size_t)node * a.ld + j + q] : T(0);
+    }
+    *reinterpret_cast<TV*>(&sX[l][jj]) = val;
   }
   __syncthreads();
   const int wave = tid / 64, lane = tid % 64, lr = lane % 16, lk = lane / 16;
   const size_t cell = ex + (size_t)a.n * (ey + (size_t)a.n * ez);
-  const T* Kc = K + cell * (size_t)a.MT * a.KS * 64;
-  for (int mt = wave; mt < a.MT; mt += kMapThreads / 64) {
-    d4 acc[NTL];
+  const T* Kc = K + cell * (size_t)MT * KS * 64 + lane;
+  d4 acc[MTI][NTL];
 #pragma unroll
-    for (int t = 0; t < NTL; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    const T* Km = Kc + (size_t)mt * a.KS * 64 + lane;
-#pragma unroll 4
-    for (int ks = 0; ks < a.KS; ++ks) {
-      const double av = (double)Km[(size_t)ks * 64];
+  for (int i = 0; i < MTI; ++i)
 #pragma unroll
-      for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av, sX[ks * 4 + lk][t * 16 + lr], acc[t]);
+    for (int t = 0; t < NTL; ++t) acc[i][t] = d4{0.0, 0.0, 0.0, 0.0};
+  // tiles beyond MT (the last wavefronts' missing ones) read tile MT - 1 and are not stored
+  const T* Km[MTI];
+#pragma unroll
+  for (int i = 0; i < MTI; ++i) Km[i] = Kc + (size_t)min(wave + NW * i, MT - 1) * KS * 64;
+  // A fragments one step ahead in registers
+  T an[MTI];
+#pragma unroll
+  for (int i = 0; i < MTI; ++i) an[i] = Km[i][0];
+  for (int ks = 0; ks < KS; ++ks) {
+    double av[MTI], bv[NTL];
+#pragma unroll
+    for (int i = 0; i < MTI; ++i) av[i] = (double)an[i];
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int i = 0; i < MTI; ++i) an[i] = Km[i][(size_t)(ks + 1) * 64];
     }
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) bv[t] = (double)sX[ks * 4 + lk][t * 16 + lr];
+#pragma unroll
+    for (int i = 0; i < MTI; ++i)
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) acc[i][t] = mfma16(av[i], bv[t], acc[i][t]);
+  }
+#pragma unroll
+  for (int i = 0; i < MTI; ++i) {
+    const int mt = wave + NW * i;
+    if (mt >= MT) continue;
 #pragma unroll
     for (int t = 0; t < NTL; ++t) {
       const int j = j0 + t * 16 + lr;
@@ -397,16 +439,29 @@ __global__ __launch_bounds__(kMapThreads) void mapped_cell_kernel(const MapApply
         const long long node = sNode[row];
         if (node < 0) continue;
         const size_t idx = (size_t)node * a.ld + j;
-        Y[idx] = (T)((double)Y[idx] + cs * acc[t][r]);
+        Y[idx] = (T)((double)Y[idx] + cs * acc[i][t][r]);
       }
     }
   }
 }
 
+// Eight wavefronts instead of four when a workgroup's LDS block exceeds 80 KB (one workgroup
+// per CU) or when four wavefronts would each hold more than 8 accumulator tiles.
+template <typename T, int P, int NTL>
+fe_status launch_class(MapApply& a, long long grid, hipStream_t s) {
+  constexpr int NP = (P + 1) * (P + 1) * (P + 1), NP4 = (NP + 3) / 4 * 4, MT = (NP + 15) / 16;
+  constexpr int JC = 16 * NTL, JP = JC + ((JC == 32 || (JC == 64 && sizeof(T) == 4)) ? 16 : 0);
+  constexpr int NT = ((size_t)NP4 * JP * sizeof(T) > 80 * 1024 || ((MT + 3) / 4) * NTL > 8) ? 512 : 256;
+  hipLaunchKernelGGL((mapped_cell_kernel<T, P, NTL, NT>), dim3((unsigned)grid), dim3(NT), 0, s, a);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 template <typename T, int P>
 fe_status launch_cells(const Mesh& m, MapApply& a, hipStream_t s) {
-  const int JC = a.nv > 16 ? 32 : 16;
-  a.jchunks = (a.nv + JC - 1) / JC;
+  // columns in chunks of at most 64: the matrices stream once per chunk
+  const int ntl = std::min(4, (a.nv + 15) / 16);
+  a.jchunks = (a.nv + 16 * ntl - 1) / (16 * ntl);
   for (int cz = 0; cz < 2; ++cz)
     for (int cy = 0; cy < 2; ++cy)
       for (int cx = 0; cx < 2; ++cx) {
@@ -418,11 +473,14 @@ fe_status launch_cells(const Mesh& m, MapApply& a, hipStream_t s) {
         const int ncz = (m.n - cz + 1) / 2;
         const long long grid = (long long)a.ncx * a.ncy * ncz * a.jchunks;
         if (grid == 0) continue;
-        if (JC == 32)
-          hipLaunchKernelGGL((mapped_cell_kernel<T, P, 32>), dim3((unsigned)grid), dim3(kMapThreads), 0, s, a);
-        else
-          hipLaunchKernelGGL((mapped_cell_kernel<T, P, 16>), dim3((unsigned)grid), dim3(kMapThreads), 0, s, a);
-        INVDFT_HIP(hipGetLastError());
+        fe_status st;
+        switch (ntl) {
+          case 1: st = launch_class<T, P, 1>(a, grid, s); break;
+          case 2: st = launch_class<T, P, 2>(a, grid, s); break;
+          case 3: st = launch_class<T, P, 3>(a, grid, s); break;
+          default: st = launch_class<T, P, 4>(a, grid, s); break;
+        }
+        if (st != FE_OK) return st;
       }
   return FE_OK;
 }

@@ -70,10 +70,10 @@ def test_argument_checks_without_gpu():
     # apply timing: an empty record reads back as zero launches, a bad precision is rejected
     n, ms, b = C.c_int64(7), C.c_double(1.0), C.c_double(1.0)
     assert lib.fe_apply_timing(1) == _lib.FE_OK
-    assert lib.fe_apply_timing_read(_lib.FE_F64, C.byref(n), C.byref(ms), C.byref(b)) == _lib.FE_OK
+    assert lib.fe_apply_timing_read(_lib.FE_F64, C.byref(n), C.byref(ms), C.byref(b), None) == _lib.FE_OK
     assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
     assert lib.fe_apply_timing(0) == _lib.FE_OK
-    assert lib.fe_apply_timing_read(_lib.FE_BF16, None, None, None) == _lib.FE_EINVAL
+    assert lib.fe_apply_timing_read(_lib.FE_BF16, None, None, None, None) == _lib.FE_EINVAL
     # FE_BF16 is reserved: rejected by the operators before any device work
     assert lib.ks_apply(null, None, None, None, None, 1, 1, _lib.FE_BF16, None) == _lib.FE_EINVAL
     # finite temperature: argument checks return before any arithmetic
