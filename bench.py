@@ -123,10 +123,15 @@ def host_cpu():
 
 
 def kernel_source_hash():
-    """Hash of the operator kernel source: the stored counter readings belong to it."""
+    """Hash of the operator kernels' sources (the sum-factorised apply and the mapped-mesh cell
+    products): the stored counter readings belong to it."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2510_10529_amd", "csrc", "apply.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("apply.hip", "mapped.hip"):
+        path = os.path.join(ROOT, "paper_2510_10529_amd", "csrc", name)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(prec, workload_name, deflate=0):
