@@ -51,6 +51,11 @@ The roofline then covers that apply, whose algorithmic bytes include the per-cel
 it is bound by HBM while its arithmetic intensity is below the FP64 ridge and by the FP64
 matrix cores above it.
 
+With --coldstart the script measures the forward eigensolve alone from a random block instead of
+the inverse loop: FP64 throughout, FP32 -> FP64 and bf16 -> FP32 -> FP64 (FE_BF16), each to the
+same tolerance, with every stage's passes, time and error against the FP64 solve (eigenvalues,
+density L1, residual) after it; it prints one JSON object.
+
 With --frontend the set-up also times the physics front end on the target density: the
 Hartree potential by the finite-element Poisson solve and the initial guess of Eq. 25
 (LB94 exchange + PW92 correlation, Fermi-Amaldi tail).
@@ -80,8 +85,8 @@ def log(msg):
 def apply_timing(api, mesh, v, nv, prec, reps=20):
     """Average ks_apply duration (ms) from HIP events on the launch stream."""
     import torch
-    dt = torch.float64 if prec == "f64" else torch.float32
-    X = torch.randn(mesh.n_free, nv, device=v.device, dtype=dt)
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+    X = torch.randn(mesh.n_free, nv, device=v.device, dtype=torch.float32).to(dt)
     Y = torch.empty_like(X)
     for _ in range(3):
         api.ks_apply(mesh, v, X, Y, prec=prec)
@@ -94,7 +99,7 @@ def apply_timing(api, mesh, v, nv, prec, reps=20):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    s = 8 if prec == "f64" else 4
+    s = {"f64": 8, "f32": 4, "bf16": 2}[prec]
     algo_bytes = 2 * mesh.n_free * nv * s + mesh.n_free * 8
     if getattr(mesh, "mapped_amp", None) is not None:   # the per-cell matrices stream once per apply
         npc = mesh.nodes_per_cell
@@ -150,6 +155,48 @@ def read_traffic(prec, workload_name, deflate=0):
             return 1024.0 * (float(f["fetch_kib"]) * float(f["fetch_scale"]) +
                              float(f["write_kib"]) * float(f["write_scale"]))
     return None
+
+
+def coldstart(api, mesh, W, v, X0, nocc, wl, args):
+    """Forward eigensolve from a random block: FP64, FP32 -> FP64 and bf16 -> FP32 -> FP64, with each
+    stage's passes, seconds and errors against the FP64 solve."""
+    import torch
+    tol, deg = 1e-10, wl.cheb_degree
+    zeros = torch.zeros(mesh.n_free, dtype=torch.float64, device=v.device)
+
+    def solve(prec, maxpass=400):
+        X = X0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.ks_eigensolve(mesh, v, X, nocc, deg, tol, maxpass, prec=prec, switch_tol=1e-4)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rho, _, _ = api.loss_grad(mesh, X[:, :nocc].contiguous(), [2.0] * nocc, zeros, want_B=False)
+        return r, el, rho
+
+    ref, t_ref, rho_ref = solve("f64")
+    out = {"workload": wl.name, "n_free": mesh.n_free, "nocc": nocc, "block": X0.shape[1], "cheb_degree": deg,
+           "tol": tol, "fp64": {"passes": ref.passes, "seconds": t_ref}}
+    log(f"coldstart FP64: {ref.passes} passes, {t_ref:.2f} s")
+    for prec in ("f32", "bf16"):
+        full, t_full, _ = solve(prec)
+        stages = []
+        done = 0
+        names = ("bf16", "f32", "f64")
+        for k, n in enumerate(full.stage_passes):
+            if n == 0:
+                continue
+            done += n
+            r, el, rho = solve(prec, maxpass=done)
+            eig_err = max(abs(a - b) for a, b in zip(r.eig[:nocc], ref.eig[:nocc]))
+            l1 = float((W * (rho - rho_ref).abs()).sum())
+            stages.append({"stage": names[k], "passes": n, "seconds_cumulative": el, "eig_err_Ha": eig_err,
+                           "density_L1": l1, "max_residual": max(r.res[:nocc])})
+            log(f"coldstart {prec}: after {names[k]} ({n} passes, {el:.2f} s): eig err {eig_err:.2e} Ha, "
+                f"density L1 {l1:.2e}, residual {max(r.res[:nocc]):.2e}")
+        out[prec] = {"passes": full.passes, "seconds": t_full, "stage_passes": full.stage_passes,
+                     "speedup_vs_fp64": t_ref / t_full, "stages": stages}
+    print(json.dumps(out), flush=True)
 
 
 def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, step_len, vxc=None):
@@ -212,6 +259,8 @@ def main():
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
                          "and f64d paths (default: the block's buffer columns; 0: off). The f64 path always keeps "
                          "the diagonal preconditioner.")
+    ap.add_argument("--coldstart", action="store_true",
+                    help="time the eigensolve from a random block in FP64, FP32 and bf16 stages (no inverse loop)")
     ap.add_argument("--frontend", action="store_true",
                     help="time the Hartree solve and the initial guess on the target density")
     ap.add_argument("--graded", type=float, default=0.0,
@@ -272,7 +321,7 @@ def main():
     del xa, ya
     if args.apply_only:
         out = {}
-        for prec, cols in (("f64", nocc), ("f32", nv)):
+        for prec, cols in (("f64", nocc), ("f32", nv), ("bf16", nv)):
             ms, b = apply_timing(api, mesh, v_fixed, cols, prec, reps=args.reps)
             out[f"ks_apply_{prec}"] = {"columns": cols, "ms": ms, "algorithmic_bytes": b,
                                        "GBps": b / ms / 1e6, "hbm_frac": b / ms / 1e6 / HBM_PEAK_GBS}
@@ -280,6 +329,9 @@ def main():
         print(json.dumps({"workload": wl.name, "n_free": mesh.n_free, **out}), flush=True)
         return
     X0 = torch.tensor(random_block(mesh.n_free, nv, 1000 + args.config), device=dev)
+    if args.coldstart:
+        coldstart(api, mesh, W, v_fixed + v_star, X0, nocc, wl, args)
+        return
 
     # target density rho_data = rho(v_fixed + v*) (untimed set-up)
     t0 = time.perf_counter()

@@ -35,10 +35,12 @@
  * concurrently.
  *
  * Precision: FE_F64 -> double blocks and FP64 arithmetic. FE_F32 -> float
- * blocks, FP32 arithmetic. FE_BF16 is reserved: every operation returns
- * FE_EINVAL for it (a bfloat16 contraction was considered for the filter and
- * not built: its 8-bit mantissa sits above the residual level the warm-started
- * filter works at, and the sum-factorised apply has no matrix-core shape).
+ * blocks, FP32 arithmetic. FE_BF16 -> bfloat16 blocks (2 bytes per element:
+ * the upper 16 bits of an IEEE binary32), widened to FP32 on load, FP32
+ * arithmetic and accumulation, rounded to nearest (ties to even) on store;
+ * taken by ks_apply, cheb_filter and ks_eigensolve on uniform and graded
+ * meshes (the sum-factorised apply has no matrix-core shape, so it runs on
+ * the vector ALU like FP32). Every other call returns FE_EINVAL for it.
  * Potentials, weights, densities, Gram matrices, eigenvalues and every
  * reduction are always FP64.
  *
@@ -156,7 +158,8 @@ const char* fe_last_error(void);
  *   v: N_f doubles (always FP64). shift_h: nv host doubles or NULL (no shift),
  *   at most 256 columns when given. X, Y: N_f x ld blocks of the precision's
  *   type; Y must not alias X.
- * prec: FE_F64 or FE_F32 (FE_EINVAL otherwise). */
+ * prec: FE_F64, FE_F32, or FE_BF16 (uniform and graded meshes); FE_EINVAL
+ * otherwise. */
 fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const void* X, void* Y,
                    int nv, int ld, fe_prec prec, void* stream);
 
@@ -166,7 +169,8 @@ fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const v
  *   p_m(lambda) = T_m((lambda - c)/e) / T_m((a0 - c)/e),
  * which damps [a, b] and keeps the columns O(1) near a0 < a.
  *   degree >= 1, a < b, a0 < a. work: fe_workspace_bytes(FE_OP_CHEB_FILTER, ld).
- * prec: FE_F64 or FE_F32 (X's type follows prec; FE_EINVAL otherwise). */
+ * prec: FE_F64, FE_F32 or FE_BF16 (X's type follows prec; every step of the
+ * recurrence is rounded to it; FE_EINVAL otherwise). */
 fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, double b, double a0,
                       void* X, int nv, int ld, fe_prec prec, void* work, void* stream);
 
@@ -186,21 +190,26 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
  * block X (nv > nocc; start from a random or warm block) until
  * max_{i < nocc} ||H~ x_i - eig_i x_i|| <= tol or maxpass passes. The filter
  * bounds are b = kinetic bound + max(v), a = largest Ritz value, a0 = smallest.
- * prec selects the filter precision (FE_F64 / FE_F32; FE_EINVAL otherwise); with a
- * reduced precision the passes switch to FP64 once the residual is below
- * `switch_tol` (or stops falling), so the final accuracy is FP64's. Rayleigh-Ritz
+ * prec selects the filter precision (FE_F64 / FE_F32 / FE_BF16; FE_EINVAL
+ * otherwise); with a reduced precision the passes switch to FP64 once the
+ * residual is below `switch_tol` (or stops falling), so the final accuracy is
+ * FP64's. FE_BF16 (uniform and graded meshes) starts a stage lower: bf16 passes
+ * (the block rounded to nearest even) until the residual stops halving or is
+ * below switch_tol, then FP32 passes as above, then FP64. Rayleigh-Ritz
  * is FP64. Locking: a pass filters only the columns from the first leading Ritz
  * pair whose residual is above tol (rounded down to a multiple of 8); the pairs
  * before it are left as they are (also in FP64 during a reduced-precision pass)
  * and still enter the Rayleigh-Ritz of the whole block. A reduced-precision pass
  * locks against max(tol, switch_tol) instead of tol.
  *   eig_h: nv host doubles (Ritz values); resnorm_h: nv host doubles.
- *   passes_h: number of passes done (nullable).
+ *   passes_h: number of passes done (nullable); stage_passes_h: 3 host ints
+ *   (nullable), the passes done in bf16, FP32 and FP64.
  * Returns FE_ENOCONV if maxpass was reached (X, eig_h, resnorm_h valid).
  * work: fe_workspace_bytes(FE_OP_EIGENSOLVE, ld, prec). */
 fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld, int nocc,
                         int degree, double tol, int maxpass, fe_prec prec, double switch_tol,
-                        double* eig_h, double* resnorm_h, int* passes_h, void* work, void* stream);
+                        double* eig_h, double* resnorm_h, int* passes_h, int* stage_passes_h, void* work,
+                        void* stream);
 
 /* --------------------------------------------------------- adjoint_solve --
  * Solves, for all i < nocc together, (H~ - eps_i) q_i = b_i with Psi^T q_i = 0

@@ -40,7 +40,7 @@ SIGNATURES = {
                               C.c_int, vp, vp]),
     "rayleigh_ritz": (C.c_int, [vp, vp, vp, dp, dp, C.c_int, C.c_int, vp, vp]),
     "ks_eigensolve": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
-                                C.c_double, dp, dp, ip, vp, vp]),
+                                C.c_double, dp, dp, ip, ip, vp, vp]),
     "adjoint_solve": (C.c_int, [vp, vp, vp, dp, C.c_int, vp, vp, C.c_double, C.c_int, ip, dp, C.c_int, vp, vp]),
     "adjoint_solve_deflated": (C.c_int, [vp, vp, vp, dp, C.c_int, vp, dp, C.c_int, vp, vp, C.c_double, C.c_int, ip,
                                          dp, vp, vp]),

@@ -13,7 +13,7 @@ import torch
 from . import _lib as L
 
 PREC = {"f64": L.FE_F64, "f32": L.FE_F32, "bf16": L.FE_BF16}
-DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}   # bf16: torch's bfloat16 storage
 
 
 def _stream():
@@ -192,6 +192,7 @@ class EigResult:
     res: list
     passes: int
     status: int
+    stage_passes: tuple = (0, 0, 0)      # passes in bf16, FP32, FP64
 
 
 def ks_eigensolve(mesh: Mesh, v, X, nocc: int, degree: int, tol: float, maxpass: int, prec: str = "f64",
@@ -204,11 +205,12 @@ def ks_eigensolve(mesh: Mesh, v, X, nocc: int, degree: int, tol: float, maxpass:
     eig = (C.c_double * nv)()
     res = (C.c_double * nv)()
     passes = C.c_int()
+    stages = (C.c_int * 3)()
     st = L.load().ks_eigensolve(mesh.handle, _ptr(v), _ptr(X), nv, ld, int(nocc), int(degree), float(tol),
-                                int(maxpass), PREC[prec], float(switch_tol), eig, res, C.byref(passes), _ptr(work),
-                                _stream())
+                                int(maxpass), PREC[prec], float(switch_tol), eig, res, C.byref(passes), stages,
+                                _ptr(work), _stream())
     L.check(st, "ks_eigensolve", allow=allow)
-    return EigResult(list(eig), list(res), passes.value, st)
+    return EigResult(list(eig), list(res), passes.value, st, tuple(stages))
 
 
 @dataclass

@@ -73,7 +73,7 @@ fe_status check_block(const void* X, const char* name, int nv, int ld) {
   return FE_OK;
 }
 
-size_t elem_size(fe_prec p) { return p == FE_F64 ? sizeof(double) : sizeof(float); }
+size_t elem_size(fe_prec p) { return p == FE_F64 ? sizeof(double) : p == FE_F32 ? sizeof(float) : sizeof(bf16_t); }
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
@@ -854,7 +854,7 @@ fe_status ks_apply(fe_mesh mesh, const double* v, const double* shift_h, const v
   if ((st = check_block(Y, "Y", nv, ld)) != FE_OK) return st;
   if (!v) return fail(FE_EINVAL, "ks_apply: v is NULL");
   if (X == Y) return fail(FE_EINVAL, "ks_apply: Y must not alias X");
-  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "ks_apply: unsupported precision");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16) return fail(FE_EINVAL, "ks_apply: unsupported precision");
   ApplyArgs aa{};
   aa.X = X;
   aa.Y = Y;
@@ -875,7 +875,8 @@ fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, doubl
   if (!work) return fail(FE_EINVAL, "cheb_filter: work is NULL");
   if (degree < 1) return fail(FE_EINVAL, "cheb_filter: degree must be >= 1");
   if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "cheb_filter: need a0 < a < b");
-  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "cheb_filter: unsupported precision");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16)
+    return fail(FE_EINVAL, "cheb_filter: unsupported precision");
   return filter_impl(mesh->m, v, degree, a, b, a0, X, nv, ld, prec, work, S(stream));
 }
 
@@ -890,15 +891,17 @@ fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h,
 
 fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld, int nocc, int degree, double tol,
                         int maxpass, fe_prec prec, double switch_tol, double* eig_h, double* resnorm_h,
-                        int* passes_h, void* work, void* stream) {
+                        int* passes_h, int* stage_passes_h, void* work, void* stream) {
   if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
   fe_status st;
   if ((st = check_block(X, "X", nv, ld)) != FE_OK) return st;
   if (!v || !work || !eig_h || !resnorm_h) return fail(FE_EINVAL, "ks_eigensolve: v, work, eig_h, resnorm_h required");
   if (nocc < 1 || nocc >= nv) return fail(FE_EINVAL, "ks_eigensolve: need 1 <= nocc < nv");
   if (degree < 1 || maxpass < 0) return fail(FE_EINVAL, "ks_eigensolve: degree >= 1 and maxpass >= 0 required");
-  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "ks_eigensolve: unsupported precision");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16)
+    return fail(FE_EINVAL, "ks_eigensolve: unsupported precision");
   const Mesh& m = mesh->m;
+  if (prec == FE_BF16 && m.mapped) return fail(FE_EINVAL, "ks_eigensolve: FE_BF16 needs a uniform or graded mesh");
   hipStream_t s = S(stream);
   Bump bp(work);
   EigWork w = eig_layout(bp, m, nv, ld, prec);
@@ -909,10 +912,12 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
   const double b = m.kin_bound + vmax;
   if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
   int pass = 0;
+  int stage_passes[3] = {0, 0, 0};   // FP64, FP32, bf16 passes
   bool conv = false;
-  // reduced-precision filter passes until the residual is below switch_tol or stops
-  // improving (its rounding floor), then FP64 passes
-  bool low = prec != FE_F64;
+  // Reduced-precision filter passes until the residual is below switch_tol or stops improving
+  // (its rounding floor), then FP64 passes. FE_BF16 starts one stage lower: bf16 passes until
+  // they stop halving the residual (or it is below switch_tol), then FP32 as above.
+  fe_prec stage = prec;
   double rprev = 1e300;
   for (;;) {
     double rmax = 0.0;
@@ -924,7 +929,12 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     if (pass >= maxpass) break;
     const double a = eig_h[nv - 1], a0 = eig_h[0];
     if (!(a < b) || !(a0 < a)) return fail(FE_EINVAL, "ks_eigensolve: degenerate filter interval");
-    if (low && (rmax <= switch_tol || rmax > 0.5 * rprev)) low = false;
+    if (stage == FE_BF16 && (rmax <= switch_tol || rmax > 0.5 * rprev)) {
+      stage = FE_F32;
+      rprev = 1e300;     // the FP32 stage judges its own progress
+    }
+    if (stage == FE_F32 && (rmax <= switch_tol || rmax > 0.5 * rprev)) stage = FE_F64;
+    const bool low = stage != FE_F64;
     rprev = rmax;
     // Locking: the leading Ritz pairs that already meet tol are not filtered again (rounded
     // down to a multiple of 8 columns, so that the filtered sub-block keeps 16-byte aligned
@@ -937,7 +947,14 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     while (j0 < nocc && resnorm_h[j0] <= lock_tol) ++j0;
     j0 &= ~7;
     const int nfilt = nv - j0;
-    if (low) {
+    if (stage == FE_BF16) {
+      bf16_t* Xb = reinterpret_cast<bf16_t*>(w.Xf);
+      if ((st = cast_block_to_bf16(X, Xb, (int64_t)m.nf * ld, s)) != FE_OK) return st;
+      if ((st = filter_impl(m, v, degree, a, b, a0, Xb + j0, nfilt, ld, FE_BF16,
+                            static_cast<bf16_t*>(static_cast<void*>(w.filt)) + j0, s)) != FE_OK)
+        return st;
+      if ((st = cast_cols_bf16_to_f64(Xb, X, m.nf, ld, j0, s)) != FE_OK) return st;
+    } else if (low) {
       if ((st = cast_block_to_f32(X, w.Xf, (int64_t)m.nf * ld, s)) != FE_OK) return st;
       if ((st = filter_impl(m, v, degree, a, b, a0, w.Xf + j0, nfilt, ld, FE_F32,
                             static_cast<float*>(static_cast<void*>(w.filt)) + j0, s)) != FE_OK)
@@ -954,8 +971,14 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
     }
     if ((st = rr_impl(m, v, X, eig_h, resnorm_h, nv, ld, w.rr, s)) != FE_OK) return st;
     ++pass;
+    ++stage_passes[stage == FE_F64 ? 0 : stage == FE_F32 ? 1 : 2];
   }
   if (passes_h) *passes_h = pass;
+  if (stage_passes_h) {
+    stage_passes_h[0] = stage_passes[2];
+    stage_passes_h[1] = stage_passes[1];
+    stage_passes_h[2] = stage_passes[0];
+  }
   if (!conv) return fail(FE_ENOCONV, "ks_eigensolve: residual tolerance not reached in maxpass passes");
   if (eig_h[nocc] - eig_h[nocc - 1] < 1e-6) return fail(FE_EGAP, "ks_eigensolve: no gap at the Fermi level");
   return FE_OK;

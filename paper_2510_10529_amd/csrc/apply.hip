@@ -57,6 +57,37 @@ struct KParams {
   double colshift[kMaxShiftCols];
 };
 
+// Storage and arithmetic types: FP64 and FP32 blocks are computed in their own precision;
+// bf16 blocks (FE_BF16: bit patterns of the upper half of an FP32) are widened to FP32 on
+// load and rounded to nearest even on store.
+template <typename T>
+struct Calc {
+  using type = T;
+};
+template <>
+struct Calc<bf16_t> {
+  using type = float;
+};
+template <typename T>
+__device__ __forceinline__ typename Calc<T>::type widen(T x) {
+  return x;
+}
+template <>
+__device__ __forceinline__ float widen<bf16_t>(bf16_t x) {
+  return __uint_as_float((unsigned)x << 16);
+}
+template <typename T>
+__device__ __forceinline__ T narrow(typename Calc<T>::type x) {
+  return x;
+}
+template <>
+__device__ __forceinline__ bf16_t narrow<bf16_t>(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
 // Tile shape per order: BEX x BEY cells per workgroup in x and y (a z-range of
 // cells is marched), chosen by measurement. Larger tiles read less halo per owned
 // node but cost LDS and registers: at P = 5 in FP64 the 2 x 2 tile takes about
@@ -181,7 +212,7 @@ __device__ __forceinline__ void z_accumulate_graded(int k, const CT (&cM)[NU], c
 
 template <typename T, int P, int J, int NT, bool GR>
 __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
-  using CT = T;  // compute type = storage type (FP64 or FP32)
+  using CT = typename Calc<T>::type;  // compute type: the storage type, FP32 for bf16 storage
   constexpr int P1 = P + 1;
   constexpr int BEX = TileShape<P, T>::BEX, BEY = TileShape<P, T>::BEY;
   constexpr int BX = BEX * P, BY = BEY * P;  // owned nodes per tile edge
@@ -346,7 +377,12 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       if (c < NCHUNK) {
         const int part = c % CPN;
         const int r = c / CPN;
-        *reinterpret_cast<T16*>(&sIn[r / NXN][r % NXN][part * EPC]) = pre[t];
+        if constexpr (sizeof(T) == sizeof(CT)) {
+          *reinterpret_cast<T16*>(&sIn[r / NXN][r % NXN][part * EPC]) = pre[t];
+        } else {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) sIn[r / NXN][r % NXN][part * EPC + e] = widen<T>(pre[t][e]);
+        }
       }
     }
 #pragma unroll
@@ -563,13 +599,13 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             const int gzo = ez * P + i;
-            zv[i] = (Z && node_ok(gzo)) ? Z[base + (long long)(gzo - 1) * pstride] : CT(0);
+            zv[i] = (Z && node_ok(gzo)) ? widen<T>(Z[base + (long long)(gzo - 1) * pstride]) : CT(0);
           }
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             const int gzo = ez * P + i;
             if (!node_ok(gzo)) continue;
-            Y[base + (long long)(gzo - 1) * pstride] = scale * acc[c][i] + (CT)prm.beta * zv[i];
+            Y[base + (long long)(gzo - 1) * pstride] = narrow<T>(scale * acc[c][i] + (CT)prm.beta * zv[i]);
           }
         }
       }
@@ -608,7 +644,7 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
 // two barriers; the x-pass also stores the diagonal term of the owned nodes.
 template <typename T, int P, int J, int BEX, int BEY, int NT>
 __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
-  using CT = T;
+  using CT = typename Calc<T>::type;
   constexpr int BX = BEX * P, BY = BEY * P;  // owned nodes per tile edge
   constexpr int NYI = BY + P + 1;            // input rows (owned + halo)
   constexpr int NXN = BX + P + 1;            // input nodes per row (owned + halo)
@@ -743,7 +779,12 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
       if (c < NCHUNK) {
         const int part = c % CPN;
         const int r = c / CPN;
-        *reinterpret_cast<T16*>(&sIn[r / NXN][r % NXN][part * EPC]) = pre[t];
+        if constexpr (sizeof(T) == sizeof(CT)) {
+          *reinterpret_cast<T16*>(&sIn[r / NXN][r % NXN][part * EPC]) = pre[t];
+        } else {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) sIn[r / NXN][r % NXN][part * EPC + e] = widen<T>(pre[t][e]);
+        }
       }
     }
 #pragma unroll
@@ -856,13 +897,13 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
 #pragma unroll
             for (int i = 0; i < P; ++i) {
               const int gzo = ez * P + i;
-              zv[i] = (Z && node_ok(gzo)) ? Z[base + (long long)(gzo - 1) * pstride] : CT(0);
+              zv[i] = (Z && node_ok(gzo)) ? widen<T>(Z[base + (long long)(gzo - 1) * pstride]) : CT(0);
             }
 #pragma unroll
             for (int i = 0; i < P; ++i) {
               const int gzo = ez * P + i;
               if (!node_ok(gzo)) continue;
-              Y[base + (long long)(gzo - 1) * pstride] = scale * acc[c][i] + (CT)prm.beta * zv[i];
+              Y[base + (long long)(gzo - 1) * pstride] = narrow<T>(scale * acc[c][i] + (CT)prm.beta * zv[i]);
             }
           }
         }
@@ -944,16 +985,17 @@ fe_status launch_p_graded(const Mesh& m, KParams& prm, hipStream_t s) {
 
 template <typename T, int J>
 fe_status launch_p(const Mesh& m, KParams& prm, hipStream_t s) {
-  // (FP32 graded: 8-column chunks; 16 would cost the second wave per SIMD at p = 5)
-  if (m.graded) return launch_p_graded<T, (sizeof(T) == 4 ? 8 : J)>(m, prm, s);
+  // (FP32 and bf16 graded: 8-column chunks; 16 would cost the second wave per SIMD at p = 5)
+  if (m.graded) return launch_p_graded<T, (sizeof(T) < 8 ? 8 : J)>(m, prm, s);
   switch (m.p) {
     case 1: return launch_typed<T, 1, J>(m, prm, s);
     case 2: return launch_typed<T, 2, J>(m, prm, s);
     case 3: return launch_typed<T, 3, J>(m, prm, s);
     case 4: return launch_typed<T, 4, J>(m, prm, s);
     case 5:
-      // FP32: merged y/z kernel on 3 x 1 cell tiles (faster at this order); FP64: separate passes
-      if constexpr (sizeof(T) == 4) return launch_yz<T, 5, J, 3, 1>(m, prm, s);
+      // FP32 arithmetic (FP32 or bf16 storage): merged y/z kernel on 3 x 1 cell tiles (faster at
+      // this order); FP64: separate passes
+      if constexpr (sizeof(T) < 8) return launch_yz<T, 5, J, 3, 1>(m, prm, s);
       else return launch_typed<T, 5, J>(m, prm, s);
     case 6: return launch_typed<T, 6, J>(m, prm, s);
     case 7: return launch_typed<T, 7, J>(m, prm, s);
@@ -1004,7 +1046,8 @@ fe_status apply_timing(int enable) {
 }
 
 fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns) {
-  if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "fe_apply_timing_read: prec must be FE_F64 or FE_F32");
+  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16)
+    return fail(FE_EINVAL, "fe_apply_timing_read: prec must be FE_F64, FE_F32 or FE_BF16");
   int64_t n = 0;
   double t = 0.0, b = 0.0, cl = 0.0;
   for (auto& r : g_timing.rec) {
@@ -1031,7 +1074,7 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
   // algorithmic bytes: X read, Y written, Z read when given (the Chebyshev term), v read
   const double blocks = a.Z ? 3.0 : 2.0;
   TimedLaunch t{g_timing.take(), g_timing.take(), (int)prec,
-                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : 4.0) + 8.0) +
+                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : prec == FE_F32 ? 4.0 : 2.0) + 8.0) +
                     (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0),
                 (double)a.nv};
   if (!t.start || !t.stop) return fail(FE_EDEVICE, "ks_apply timing: hipEventCreate failed");
@@ -1075,6 +1118,7 @@ static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec
   switch (prec) {
     case FE_F64: return launch_p<double, 8>(m, prm, s);
     case FE_F32: return launch_p<float, 16>(m, prm, s);
+    case FE_BF16: return launch_p<bf16_t, 16>(m, prm, s);
     default: return fail(FE_EINVAL, "ks_apply: precision not supported by this operator");
   }
 }

@@ -294,6 +294,33 @@ __global__ void cast_kernel(const TS* __restrict__ src, TD* __restrict__ dst, lo
     dst[i] = (TD)src[i];
 }
 
+// bf16 <-> wider: round to nearest, ties to even, on the FP32 value (an FP64 value is first
+// rounded to FP32; NaN stays a quiet NaN, overflow goes to infinity as rounding dictates)
+__device__ __forceinline__ bf16_t bf16_from_f32(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(bf16_t b) { return __uint_as_float((unsigned)b << 16); }
+
+__global__ void cast_to_bf16_kernel(const double* __restrict__ src, bf16_t* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = bf16_from_f32((float)src[i]);
+}
+
+__global__ void cast_cols_from_bf16_kernel(const bf16_t* __restrict__ src, double* __restrict__ dst, long long nrow,
+                                           int ld, int c0) {
+  const int w = ld - c0;
+  const long long total = nrow * w;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / w;
+    const long long idx = r * ld + c0 + (e - r * w);
+    dst[idx] = (double)bf16_to_f32(src[idx]);
+  }
+}
+
 // columns [c0, ld) of an nrow x ld row-major block (the trailing columns of every row)
 template <typename TS, typename TD>
 __global__ void cast_cols_kernel(const TS* __restrict__ src, TD* __restrict__ dst, long long nrow, int ld, int c0) {
@@ -468,6 +495,20 @@ fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStr
 fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL((cast_kernel<float, double>), dim3(stream_grid(count)), dim3(256), 0, s, src, dst,
                      (long long)count);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status cast_block_to_bf16(const double* src, bf16_t* dst, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(cast_to_bf16_kernel, dim3(stream_grid(count)), dim3(256), 0, s, src, dst, (long long)count);
+  INVDFT_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status cast_cols_bf16_to_f64(const bf16_t* src, double* dst, int64_t nrow, int ld, int c0, hipStream_t s) {
+  if (c0 < 0 || c0 >= ld) return fail(FE_EINVAL, "cast_cols: column range");
+  hipLaunchKernelGGL(cast_cols_from_bf16_kernel, dim3(stream_grid(nrow * (ld - c0))), dim3(256), 0, s, src, dst,
+                     (long long)nrow, ld, c0);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

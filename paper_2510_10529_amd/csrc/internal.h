@@ -127,8 +127,14 @@ fe_status colresid(const double* HX, const double* X, const double* lam, int ld,
 fe_status dot1(const double* x, const double* y, int64_t n, double* out, void* work, hipStream_t s);
 fe_status max1(const double* x, int64_t n, double* out, void* work, hipStream_t s);
 
+// bf16 storage: the upper 16 bits of an IEEE binary32 (FE_BF16 blocks hold these bit patterns)
+typedef unsigned short bf16_t;
+
 // Kernels used by the Krylov and loss/gradient code (defined in blockops.hip).
 fe_status cast_block_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
+// FP64 -> bf16 with round-to-nearest-even; bf16 -> FP64 (exact) of columns [c0, ld)
+fe_status cast_block_to_bf16(const double* src, bf16_t* dst, int64_t count, hipStream_t s);
+fe_status cast_cols_bf16_to_f64(const bf16_t* src, double* dst, int64_t nrow, int ld, int c0, hipStream_t s);
 fe_status cast_block_to_f64(const float* src, double* dst, int64_t count, hipStream_t s);
 // columns [c0, ld) of an nrow x ld block (row pitch ld in both)
 fe_status cast_cols_to_f64(const float* src, double* dst, int64_t nrow, int ld, int c0, hipStream_t s);

@@ -647,7 +647,7 @@ fe_status launch_apply_mapped(const Mesh& m, const ApplyArgs& aa, fe_prec prec, 
     a.K = m.d_Ke32;
     return launch_mapped_typed<float>(m, a, s);
   }
-  return fail(FE_EINVAL, "ks_apply: precision not supported by this operator");
+  return fail(FE_EINVAL, "ks_apply: mapped meshes take FE_F64 or FE_F32 blocks");
 }
 
 size_t mapped_matrix_bytes(const Mesh& m, fe_prec prec) {

@@ -73,9 +73,8 @@ def test_argument_checks_without_gpu():
     assert lib.fe_apply_timing_read(_lib.FE_F64, C.byref(n), C.byref(ms), C.byref(b), None) == _lib.FE_OK
     assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
     assert lib.fe_apply_timing(0) == _lib.FE_OK
-    assert lib.fe_apply_timing_read(_lib.FE_BF16, None, None, None, None) == _lib.FE_EINVAL
-    # FE_BF16 is reserved: rejected by the operators before any device work
-    assert lib.ks_apply(null, None, None, None, None, 1, 1, _lib.FE_BF16, None) == _lib.FE_EINVAL
+    assert lib.fe_apply_timing_read(3, None, None, None, None) == _lib.FE_EINVAL     # no such precision
+    assert lib.ks_apply(null, None, None, None, None, 1, 1, _lib.FE_BF16, None) == _lib.FE_EINVAL   # NULL mesh
     # finite temperature: argument checks return before any arithmetic
     eig = (C.c_double * 3)(-1.0, 0.0, 1.0)
     bad = (C.c_double * 3)(0.0, -1.0, 1.0)

@@ -230,13 +230,15 @@ def test_adjoint_noconv_status():
     assert all(i == 1 for i in ar.iters)
 
 
-def test_bf16_is_rejected():
-    """FE_BF16 is reserved: the operators refuse it before any device work."""
+def test_bf16_is_refused_where_not_supported():
+    """FE_BF16 blocks are taken by the apply, the filter and the eigensolver only."""
     from paper_2510_10529_amd import _lib
     api = _api()
     m, om = _mesh_pair(2, 6, 4.0)
-    X = torch.zeros((om.n_free, 4), dtype=torch.float32, device=DEV)
+    k = 4
+    Psi = torch.zeros((om.n_free, k), dtype=torch.float64, device=DEV)
     v = torch.zeros(om.n_free, dtype=torch.float64, device=DEV)
     with pytest.raises(_lib.FEError) as e:
-        api.ks_apply(m, v, X, prec="bf16")
+        api.adjoint_solve(m, v, Psi, [0.0] * k, Psi.clone(), prec="bf16", work=torch.empty(1 << 20, dtype=torch.uint8,
+                                                                                         device=DEV))
     assert e.value.status == _lib.FE_EINVAL
