@@ -259,6 +259,9 @@ def main():
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
                          "and f64d paths (default: the block's buffer columns; 0: off). The f64 path always keeps "
                          "the diagonal preconditioner.")
+    ap.add_argument("--buffer", type=int, default=-1,
+                    help="ChFSI buffer columns above the occupied ones (default: the workload's max(4, 0.2 N_occ), "
+                         "with the block rounded up to a multiple of 8 columns, at most 64, at zero temperature)")
     ap.add_argument("--coldstart", action="store_true",
                     help="time the eigensolve from a random block in FP64, FP32 and bf16 stages (no inverse loop)")
     ap.add_argument("--frontend", action="store_true",
@@ -297,8 +300,11 @@ def main():
     v_fixed = torch.tensor(wl.v_fixed(xyz_h), device=dev)
     v_star = torch.tensor(wl.v_xc_target(xyz_h), device=dev)
     del xyz_h
-    nocc, nv = wl.n_occ, wl.n_occ + wl.n_buf
     kT = args.kT
+    nocc, nv = wl.n_occ, wl.n_occ + (wl.n_buf if args.buffer < 0 else args.buffer)
+    if args.buffer < 0 and kT <= 0:
+        # whole 8-column chunks of the FP64 apply, and more Ritz vectors to deflate the adjoint
+        nv = max(nv, min(64, (nv + 7) // 8 * 8))
     nconv = nocc
     if kT > 0:
         nv += 4
