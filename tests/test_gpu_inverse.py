@@ -91,4 +91,34 @@ def test_lbfgs_30_steps_recovers_towards_known_potential():
     assert all(np.isfinite(losses))
     assert all(b <= a for a, b in zip(losses, losses[1:]))      # Armijo steps only
     assert losses[-1] <= 1e-2 * losses[0]
-    assert rms(uT) < 0.85 * rms(u0)
+    assert rms(uT) < 0.78 * rms(u0)          # measured 0.747 (7.64e-2 -> 5.71e-2 Ha)
+
+
+def test_lbfgs_30_steps_on_a_linear_xc_mesh():
+    """With v_xc on the paper's linear mesh (Eq. 14; uniform 0.5 bohr cells on the inner cube,
+    growing by 1.4 outwards) the density constrains far fewer unknowns, and the same 30 steps
+    move the potential much further towards v*: measured 7.64e-2 -> 4.01e-2 Ha over rho_d >= 1e-3
+    and 8.02e-2 -> 2.19e-2 Ha over rho_d >= 1e-2."""
+    from paper_2510_10529_amd import api
+    from paper_2510_10529_amd import inverse as inv
+    from synth import vxc_vertices
+    wl, m, vf, vs, rho_d, prob0 = _problem()
+    tv = vxc_vertices(wl.half_width, 0.5, 0.5 * wl.half_width, 1.4)
+    vm = api.VxcMesh(m, tv, tv, tv)
+    prob = inv.InverseProblem(m, vf, rho_d, wl.n_elec, prob0.X, prob0.opts, vxc=vm)
+    zero = torch.zeros_like(vf)
+
+    def rms(uv, tau):
+        mask = rho_d >= tau
+        d = (vm.prolong(uv, base=zero) - vs)[mask]
+        d = d - d.mean()
+        return float(torch.sqrt((d * d).mean()))
+
+    u0 = prob.zeros_u()
+    uT, losses = inv.lbfgs(prob, u0, maxiter=30)
+    _say(f"L-BFGS 30 steps on the linear mesh ({vm.n_vertices} vertices): loss {losses[0]:.3e} -> {losses[-1]:.3e}; "
+         f"RMS over rho_d >= 1e-3 {rms(u0, 1e-3):.3e} -> {rms(uT, 1e-3):.3e}, "
+         f">= 1e-2 {rms(u0, 1e-2):.3e} -> {rms(uT, 1e-2):.3e} Ha")
+    assert all(b <= a for a, b in zip(losses, losses[1:]))
+    assert rms(uT, 1e-3) < 0.6 * rms(u0, 1e-3)
+    assert rms(uT, 1e-2) < 0.35 * rms(u0, 1e-2)
