@@ -26,7 +26,14 @@ duration. Its HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
 this same command, scaled by what the counters read for fe_axpby over 2^27
 doubles (launched at start-up as the reference), stored under profiles/ with
 the hash of the kernel source they were taken on; it is null when the kernel
-source has changed since.
+source has changed since. The same fe_axpby, timed by HIP events, gives the
+bandwidth a plain streaming kernel reaches (roofline.measured_copy_GBps),
+reported beside the 8 TB/s spec peak.
+
+minres_sweeps reports the adjoint's three fused row sweeps (passes A, B, C of
+one MINRES iteration) over the head path's timed steps, each launch timed by
+HIP events (fe_sweep_timing_read) against its algorithmic bytes; one iteration
+streams N s (3 k0 + 16 k) + 8 N bytes (k0 orbitals, k active columns).
 
 With --kT T (Ha) the same loop runs at finite temperature: Fermi-Dirac
 occupations with mu from the electron count, every orbital above the occupation
@@ -235,6 +242,7 @@ def run_path(api, inv, mesh, v_fixed, rho_d, n_elec, X0, opts, steps, warmup, st
     elapsed = time.perf_counter() - t0
     api.apply_timing(False)
     timing = {p: api.apply_timing_read(p) for p in ("f64", "f32")}      # (launches, ms, bytes, columns)
+    timing.update({f"minres_{q}": api.sweep_timing_read(q) for q in "ABC"})
     return elapsed, losses, g_first, prob, timing
 
 
@@ -323,7 +331,15 @@ def main():
     ya = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     for _ in range(2):
         api.axpby(1.0, xa, 1.0, ya)
-    torch.cuda.synchronize()
+    # the same kernel timed: the bandwidth a plain streaming kernel reaches, beside the 8 TB/s spec
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        api.axpby(1.0, xa, 1.0, ya)
+    ev1.record()
+    ev1.synchronize()
+    copy_gbs = 10 * 3 * 8 * (1 << 27) / (ev0.elapsed_time(ev1) * 1e6)
+    log(f"fe_axpby over 2^27 doubles: {copy_gbs:.0f} GB/s")
     del xa, ya
     if args.apply_only:
         out = {}
@@ -438,7 +454,8 @@ def main():
                              n_incl=prob.state.n)
         for p_, (n_, ms_, b_, _c) in timing.items():
             if n_:
-                log(f"  ks_apply {p_}: {n_} launches, {ms_:.1f} ms, {b_ / ms_ / 1e6:.0f} GB/s")
+                log(f"  {'ks_apply ' if p_ in ('f64', 'f32') else ''}{p_}: {n_} launches, {ms_:.1f} ms, "
+                    f"{b_ / ms_ / 1e6:.0f} GB/s")
         log(f"path {name}: {steps / el:.4f} iters/s  forward {prob.stats.t_forward / steps:.2f} s/step  "
             f"adjoint {prob.stats.t_adjoint / steps:.2f} s/step")
         del prob
@@ -473,7 +490,7 @@ def main():
     log(f"ks_apply f32 nv={nv}: {ms32:.3f} ms {gbs32:.0f} GB/s ; f64 nv={nocc}: {ms64:.3f} ms {gbs64:.0f} GB/s")
 
     # dominant kernel of the head path's timed steps: the apply precision with the most time
-    tim = head["timing"]
+    tim = {p: head["timing"][p] for p in ("f64", "f32")}
     dom = max(tim, key=lambda p: tim[p][1])
     n_l, ms_l, b_l, c_l = tim[dom]
     achieved = b_l / ms_l / 1e6                       # GB/s = (bytes per launch) / (ms per launch)
@@ -481,7 +498,20 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"ks_apply_{dom}", "launches": n_l, "ms_per_launch": ms_l / n_l,
-                "algorithmic_bytes_per_launch": b_l / n_l}
+                "algorithmic_bytes_per_launch": b_l / n_l,
+                "measured_copy_GBps": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs}
+    # the MINRES row sweeps of the head path's timed steps (HIP events around each pass)
+    sweeps = {}
+    for q in "ABC":
+        n_q, ms_q, b_q, c_q = head["timing"][f"minres_{q}"]
+        if n_q:
+            sweeps[q] = {"launches": n_q, "ms_per_launch": ms_q / n_q, "GBps": b_q / ms_q / 1e6,
+                         "mean_columns": c_q / n_q, "ms_total_per_step": ms_q / head["steps"]}
+    if sweeps:
+        tot_ms = sum(head["timing"][f"minres_{q}"][1] for q in "ABC")
+        tot_b = sum(head["timing"][f"minres_{q}"][2] for q in "ABC")
+        sweeps["bytes_per_iteration"] = "N s (3 k0 + 16 k) + 8 N"
+        sweeps["GBps_all_passes"] = tot_b / tot_ms / 1e6
     if args.mapped is not None:
         # dense cell products: 2 n_c n_p^2 flops per column of each launch
         s_b = 8 if dom == "f64" else 4
@@ -571,6 +601,7 @@ def main():
         **vxc_info,
         **fe_info,
         "roofline": roofline,
+        "minres_sweeps": sweeps,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

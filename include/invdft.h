@@ -178,7 +178,8 @@ fe_status cheb_filter(fe_mesh mesh, const double* v, int degree, double a, doubl
  * Rayleigh-Ritz on span(X) (Eqs. 23-24), FP64: S = X^T X = L L^T,
  * H_X = X^T H~ X, eigen-decomposition of L^{-1} H_X L^{-T} = V diag(eig) V^T,
  * X <- X L^{-T} V (orthonormal Ritz vectors, ascending Ritz values in eig_h),
- * resnorm_h[i] = || H~ x_i - eig_i x_i ||_2 (nullable).
+ * resnorm_h[i] = || H~ x_i - eig_i x_i ||_2 (nullable). Any nv: above 64
+ * columns the rotations go through a second N_f x ld block in work.
  * On FE_ENOTPD (S not positive definite) X is left unchanged.
  * work: fe_workspace_bytes(FE_OP_RAYLEIGH_RITZ, ld). Synchronises the stream. */
 fe_status rayleigh_ritz(fe_mesh mesh, const double* v, double* X, double* eig_h, double* resnorm_h,
@@ -228,7 +229,11 @@ fe_status ks_eigensolve(fe_mesh mesh, const double* v, double* X, int nv, int ld
  *   nullable) are filled on return.
  * prec: FE_F64, or FE_F32 = FP32 inner MINRES (relative tolerance
  * max(tol, 1e-4)) with FP64 iterative refinement (residuals and updates of Q in
- * FP64). nocc <= 64. Columns that have converged are dropped from the batch.
+ * FP64). nocc <= 256 in FP64, nocc <= 64 with FE_F32. Above 64 orbitals the
+ * shifts are solved in groups of at most 64 columns, each against all of Psi
+ * (the first 64 orbitals inside the fused MINRES sweeps, the others by separate
+ * projection sweeps); iters_h and relres_h keep the column order. Columns that
+ * have converged are dropped from the batch.
  * Psi, B, Q and work must be 16-byte aligned (FE_EINVAL otherwise).
  * maxit bounds the whole FP64 solve (first solve and refinement rounds
  * together, counted in iterations of the slowest column). Returns FE_ENOCONV
@@ -278,7 +283,7 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
  *   (Eqs. 7, 10, 20). Any of rho, B, loss_h may be NULL.
  * Phase 2 (Q != NULL): grad_b = sum_i psi_{b,i} q_{b,i} (Eqs. 11, 22), then
  *   grad_b = 0 where rho_data,b < tau_bc when tau_bc > 0 (Sec. 3.1.2).
- *   Psi: N_f x nocc (ld = nocc); occ_h: nocc host doubles (f_i);
+ *   Psi: N_f x nocc (ld = nocc), 1 <= nocc <= 256; occ_h: nocc host doubles (f_i);
  *   loss_h also returns the loss in phase 2 when rho is given.
  * Synchronises the stream when loss_h != NULL. work: FE_OP_LOSS_GRAD bytes. */
 fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int nocc,
@@ -382,12 +387,12 @@ fe_status fermi_occupations(const double* eig_h, int n, double n_elec, double kT
  * degenerate group the diagonal block of C is Eq. 8's overlap; between groups
  * the coupling is split symmetrically, which changes the individual adjoint
  * functions but not the gradient.
- *   Psi: N_f x n (ld = n), n <= 64; eps_h: n host doubles; rho, rho_data: N_f;
+ *   Psi: N_f x n (ld = n), n <= 256; eps_h: n host doubles; rho, rho_data: N_f;
  *   Q: N_f x n (ld = n), in/out. eta_h (nullable): out, eta of Eq. 9.
  *   C_h (nullable): out, n x n host doubles (row-major).
  * Psi, Q and work must be 16-byte aligned. work: fe_workspace_bytes(
  * FE_OP_ALONG_PSI, n). Synchronises the stream.
- * Errors: FE_EINVAL (NULL or misaligned pointers, n outside [1, 64], kT <= 0). */
+ * Errors: FE_EINVAL (NULL or misaligned pointers, n outside [1, 256], kT <= 0). */
 fe_status adjoint_along_psi(fe_mesh mesh, const double* Psi, int n, const double* eps_h, double mu, double kT,
                             double smax, const double* rho, const double* rho_data, double* Q, double* eta_h,
                             double* C_h, void* work, void* stream);
@@ -403,7 +408,7 @@ fe_status adjoint_along_psi(fe_mesh mesh, const double* Psi, int n, const double
  *     projection of B) is a fixed device array of this library,
  *     loss_grad_noalloc_max_bytes() bytes (34 MiB), one copy per GPU, held
  *     until the process ends. A call whose scratch would exceed it returns
- *     FE_EINVAL (cannot happen for nocc <= 64 on any mesh);
+ *     FE_EINVAL (cannot happen for nocc <= 256 on any mesh);
  *   - the current device must be the one the mesh was created on (FE_EINVAL).
  * It calls no hipMalloc, hipFree or allocating library routine. Every call on
  * one GPU uses that GPU's single array: calls that overlap in time on one GPU
@@ -418,29 +423,41 @@ fe_status loss_grad_noalloc(fe_mesh mesh, const double* Psi, const double* occ_h
 /* --------------------------------------------------------- block helpers --
  * Small FP64 vector kernels used by the host-side L-BFGS driver (Eq. 21):
  * fe_dot returns sum_a x_a y_a over n entries (deterministic reduction);
- * fe_axpby computes y <- alpha x + beta y. work: at least 64 KiB. */
+ * fe_axpby computes y <- alpha x + beta y (n = 0: nothing, x and y may be NULL).
+ * work: at least 64 KiB. */
 fe_status fe_dot(const double* x, const double* y, int64_t n, double* out_h, void* work, void* stream);
 fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_t n, void* stream);
 
 /* ------------------------------------------------------- apply timing ----
- * Measurement aid for the operator apply (not part of the method): while
- * enabled, every operator launch (ks_apply and the applies inside
- * cheb_filter, ks_eigensolve and adjoint_solve) is bracketed by two HIP events
- * on the stream it is launched on, so that its duration is measured without
- * synchronising the caller.
+ * Measurement aid for the operator apply and the MINRES row sweeps (not part
+ * of the method): while enabled, every operator launch (ks_apply and the
+ * applies inside cheb_filter, ks_eigensolve and adjoint_solve) and every
+ * fused MINRES pass of adjoint_solve (Sec. 3.2.2) is bracketed by two HIP
+ * events on the stream it is launched on, so that its duration is measured
+ * without synchronising the caller.
  * fe_apply_timing(enable): 1 starts a new measurement (clears the record),
  *   0 stops recording (the record is kept). Host-side, process-wide; not
  *   thread-safe while launches are in flight.
  * fe_apply_timing_read(prec, launches, ms, bytes, columns): waits for the
- *   recorded events and returns, for launches in precision prec (FE_F64 or
- *   FE_F32), their count, summed duration in milliseconds, summed algorithmic
- *   bytes (X read, Y written, Z read when the Chebyshev term is present, v read:
- *   (2 or 3) N_f nv s + 8 N_f per launch, s = 8 or 4; on a mapped mesh also the
+ *   recorded events and returns, for launches in precision prec (FE_F64,
+ *   FE_F32 or FE_BF16), their count, summed duration in milliseconds, summed
+ *   algorithmic bytes (X read, Y written, Z read when the Chebyshev term is
+ *   present, v read: (2 or 3) N_f nv s + 8 N_f per launch, s = 8, 4 or 2 bytes
+ *   per element; on a mapped mesh also the
  *   per-cell matrices of that precision) and summed column counts nv. Any
  *   output may be NULL.
- * Errors: FE_EINVAL for another prec, FE_EDEVICE for a failed event call. */
+ * fe_sweep_timing_read(pass, launches, ms, bytes, columns): the same for the
+ *   MINRES passes, pass 0 = A (Psi^T y and the two column dots), 1 = B (the new
+ *   residual, the preconditioned u, Psi^T u), 2 = C (the projected direction,
+ *   the w recurrence and the solution update); a pass's launch includes its
+ *   small fixed-order reduction. Algorithmic bytes per launch, N rows, k active
+ *   columns, k0 = nocc, s = 8 or 4: A N s (k0 + 3k), B N (s (k0 + 5k) + 8),
+ *   C N s (k0 + 8k); one iteration is N s (3 k0 + 16 k) + 8 N. columns sums k.
+ * Errors: FE_EINVAL for another prec or pass, FE_EDEVICE for a failed event
+ * call. */
 fe_status fe_apply_timing(int enable);
 fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns);
+fe_status fe_sweep_timing_read(int pass, int64_t* launches, double* ms, double* bytes, double* columns);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,7 @@ SIGNATURES = {
     "fe_axpby": (C.c_int, [C.c_double, vp, C.c_double, vp, C.c_int64, vp]),
     "fe_apply_timing": (C.c_int, [C.c_int]),
     "fe_apply_timing_read": (C.c_int, [C.c_int, i64p, dp, dp, dp]),
+    "fe_sweep_timing_read": (C.c_int, [C.c_int, i64p, dp, dp, dp]),
     "vxc_mesh_create": (C.c_int, [vp, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.POINTER(vp)]),
     "vxc_mesh_info": (C.c_int, [vp, i64p, ip]),
     "vxc_mesh_destroy": (C.c_int, [vp]),

@@ -298,6 +298,15 @@ def apply_timing_read(prec: str = "f64"):
     return n.value, ms.value, b.value, cols.value
 
 
+def sweep_timing_read(pass_: str = "A"):
+    """(launches, total ms, total algorithmic bytes, total active columns) of the recorded MINRES
+    passes A, B or C."""
+    n, ms, b, cols = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+    L.check(L.load().fe_sweep_timing_read("ABC".index(pass_), C.byref(n), C.byref(ms), C.byref(b), C.byref(cols)),
+            "fe_sweep_timing_read")
+    return n.value, ms.value, b.value, cols.value
+
+
 @dataclass
 class Occupations:
     occ: list

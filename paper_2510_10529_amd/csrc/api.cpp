@@ -130,12 +130,14 @@ size_t filter_work(const Mesh& m, int ld, fe_prec prec) { return align_up((size_
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 struct RRWork {
-  double *HX, *S, *H, *C, *lam, *res, *gw;
+  double *HX, *T, *S, *H, *C, *lam, *res, *gw;
 };
 
 RRWork rr_layout(Bump& bp, const Mesh& m, int nv, int ld) {
   RRWork w{};
   w.HX = bp.take<double>((size_t)m.nf * ld);
+  // above 64 columns the rotations are not in place: their results go through T
+  w.T = nv > 64 ? bp.take<double>((size_t)m.nf * ld) : nullptr;
   w.S = bp.take<double>((size_t)nv * nv);
   w.H = bp.take<double>((size_t)nv * nv);
   w.C = bp.take<double>((size_t)nv * nv);
@@ -147,7 +149,6 @@ RRWork rr_layout(Bump& bp, const Mesh& m, int nv, int ld) {
 
 fe_status rr_impl(const Mesh& m, const double* v, double* X, double* eig_h, double* res_h, int nv, int ld,
                   void* work, hipStream_t s) {
-  if (nv > 64) return fail(FE_EINVAL, "rayleigh_ritz: at most 64 columns are supported");
   Bump bp(work);
   RRWork w = rr_layout(bp, m, nv, ld);
   fe_status st = gram(X, ld, X, ld, m.nf, nv, nv, false, w.S, w.gw, s);
@@ -200,12 +201,19 @@ fe_status rr_impl(const Mesh& m, const double* v, double* X, double* eig_h, doub
     }
   INVDFT_HIP(hipMemcpyAsync(w.C, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
   INVDFT_HIP(hipMemcpyAsync(w.lam, lam.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
-  st = rotate(X, ld, m.nf, nv, w.C, nv, X, ld, s);
-  if (st != FE_OK) return st;
-  st = rotate(w.HX, ld, m.nf, nv, w.C, nv, w.HX, ld, s);
-  if (st != FE_OK) return st;
+  double* HX = w.HX;
+  if (!w.T) {
+    if ((st = rotate(X, ld, m.nf, nv, w.C, nv, X, ld, s)) != FE_OK) return st;
+    if ((st = rotate(HX, ld, m.nf, nv, w.C, nv, HX, ld, s)) != FE_OK) return st;
+  } else {
+    if ((st = rotate(X, ld, m.nf, nv, w.C, nv, w.T, ld, s)) != FE_OK) return st;
+    INVDFT_HIP(hipMemcpy2DAsync(X, ld * sizeof(double), w.T, ld * sizeof(double), nv * sizeof(double), m.nf,
+                                hipMemcpyDeviceToDevice, s));
+    if ((st = rotate(w.HX, ld, m.nf, nv, w.C, nv, w.T, ld, s)) != FE_OK) return st;
+    HX = w.T;
+  }
   std::vector<double> res(nv);
-  st = colresid(w.HX, X, w.lam, ld, m.nf, nv, w.res, w.gw, s);
+  st = colresid(HX, X, w.lam, ld, m.nf, nv, w.res, w.gw, s);
   if (st != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(res.data(), w.res, nv * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipStreamSynchronize(s));
@@ -250,10 +258,14 @@ struct MRWork {
   double *R64, *Y64;
   // FP64 refinement on the true residual: its right-hand side, correction and column mask
   double *rb, *dq, *mask;
+  // more than 64 orbitals: the fused passes' copy of the first 64, and one group's B and Q
+  double *Pf, *Bg, *Qg;
 };
 
-MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
+// k columns solved together (at most 64), kpsi orbitals to project against
+MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec, int kpsi = 0) {
   MRWork w{};
+  if (kpsi < k) kpsi = k;
   const size_t blk = (size_t)m.nf * k;
   const size_t es = prec == FE_F64 ? sizeof(double) : sizeof(float);
   w.R1 = bp.take<char>(blk * es);
@@ -270,7 +282,7 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
   w.d1 = bp.take<double>(k);
   w.d2 = bp.take<double>(k);
   w.bnorm = bp.take<double>(k);
-  w.pw = bp.take<double>(std::max(project_work_bytes(m.nf, k, k), coldot_work_bytes(m.nf, k)) / sizeof(double) + 1);
+  w.pw = bp.take<double>(std::max(project_work_bytes(m.nf, kpsi, k), coldot_work_bytes(m.nf, k)) / sizeof(double) + 1);
   if (prec != FE_F64) {
     w.X = bp.take<char>(blk * es);
     w.Psif = bp.take<float>(blk);
@@ -280,6 +292,19 @@ MRWork mr_layout(Bump& bp, const Mesh& m, int k, fe_prec prec) {
     w.rb = bp.take<double>(blk);
     w.dq = bp.take<double>(blk);
     w.mask = bp.take<double>((size_t)k * k);
+  }
+  return w;
+}
+
+// An adjoint solve of nocc columns: groups of at most 64 shifts, each against all nocc orbitals
+// (FP64 above 64 orbitals).
+MRWork adjoint_layout(Bump& bp, const Mesh& m, int nocc, fe_prec prec) {
+  const int k = std::min(nocc, 64);
+  MRWork w = mr_layout(bp, m, k, prec, nocc);
+  if (nocc > 64) {
+    w.Pf = bp.take<double>((size_t)m.nf * 64);
+    w.Bg = bp.take<double>((size_t)m.nf * 64);
+    w.Qg = bp.take<double>((size_t)m.nf * 64);
   }
   return w;
 }
@@ -333,9 +358,28 @@ Deflation defl_layout(Bump& bp, const Mesh& m, int k, int nb, double** Ucopy, do
   return d;
 }
 
+// The orbitals a solve projects against: Psi (N x kpsi, row pitch kpsi) in full, the block the
+// fused passes take (Pf: N x kf, kf <= 64, its own row pitch kf) and the rest (Pr: the columns of
+// Psi past Pf, kr of them, row pitch kpsi), projected by separate sweeps. Up to 64 orbitals Pf is
+// Psi and there is no rest.
 template <typename T>
-fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double* eps_h, int k0, const T* B, T* Q,
-                      double tol, int maxit, MRWork& w, std::vector<double>& iters, std::vector<double>& active,
+struct ProjSet {
+  const T* Psi;
+  int kpsi;
+  const T* Pf;
+  int kf;
+  const T* Pr;
+  int kr;
+};
+
+template <typename T>
+ProjSet<T> proj_whole(const T* Psi, int k) {
+  return ProjSet<T>{Psi, k, Psi, k, nullptr, 0};
+}
+
+template <typename T>
+fe_status minres_core(const Mesh& m, const double* v, const ProjSet<T>& ps, const double* eps_h, int k0, const T* B,
+                      T* Q, double tol, int maxit, MRWork& w, std::vector<double>& iters, std::vector<double>& active,
                       hipStream_t s, Deflation* df = nullptr) {
   const int64_t nf = m.nf;
   const bool f32 = sizeof(T) == sizeof(float);
@@ -350,15 +394,22 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
   if ((st = fill_t<T>(Wa, blk, s)) != FE_OK) return st;
   if ((st = fill_t<T>(Wb, blk, s)) != FE_OK) return st;
   const bool defl = df != nullptr;
-  const T* Pj = Psi;     // the block the fused passes project with
-  int kp = k0;
+  if (defl && ps.Pr) return fail(FE_EINVAL, "adjoint_solve: deflation needs Psi and U within 64 columns");
+  const T* Psi = ps.Psi;
+  const int kpsi = ps.kpsi;
+  const T* Pj = ps.Pf;     // the block the fused passes project with
+  int kp = ps.kf;
+  // the orbitals past the fused block: X <- X - Pr (Pr^T X) on a k-column block
+  auto project_rest = [&](T* X, int k) -> fe_status {
+    return ps.Pr ? project_out_ld(ps.Pr, kpsi, ps.kr, X, k, nf, f32, w.pw, s) : FE_OK;
+  };
   double *cR1 = nullptr, *cR2 = nullptr, *cN = nullptr;
   if (!defl) {
     if ((st = copy_bytes(B, R1, blk * sizeof(T), s)) != FE_OK) return st;
     if ((st = copy_bytes(B, R2, blk * sizeof(T), s)) != FE_OK) return st;
     // z = P D^{-1} b ; beta1 = sqrt(b.z)
     if ((st = k_precond<T>(B, w.dinv, k, nf, Z, s)) != FE_OK) return st;
-    if ((st = project_out(Psi, k0, Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
+    if ((st = project_out(Psi, kpsi, Z, k, nf, f32, w.pw, s)) != FE_OK) return st;
   } else {
     if constexpr (sizeof(T) == sizeof(double)) {
       Pj = df->V;
@@ -419,6 +470,8 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
     aa.Y = Y;
     aa.d_colscale = w.st + (size_t)mr_state_invbeta() * k;
     if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
+    // the orbitals past the fused block leave y first (P = P_f P_r: the two sets are orthogonal)
+    if ((st = project_rest(Y, k)) != FE_OK) return st;
     // one sweep: G = Psi^T y, z.y, z.r1; alfa = v.(P y - c1 r1) = v.y - c1 v.r1 (v is orthogonal to Psi)
     if ((st = minres_pass_a<T>(Pj, kp, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
     if (defl && (st = defl_d2(fw.d2, cR1, cR2, df->theta, df->eps, k, df->nb, s)) != FE_OK) return st;
@@ -434,6 +487,9 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
       cN = t;
     }
     std::swap(R1, R2);  // R1 <- old r2, R2 <- r_new
+    // u loses its part along the rest before pass C forms z = u - Pf G2; G2 = Pf^T u and r.u are
+    // unchanged by it (Pf and r are orthogonal to the rest)
+    if ((st = project_rest(Y, k)) != FE_OK) return st;
     if ((st = mr_givens(w.st, fw.d, k, tol, s)) != FE_OK) return st;
     // z_new = P u (into Y) ; w and q updates with the new rotation
     if ((st = minres_pass_c<T>(Pj, kp, Y, Z, Wb, Wa, Qw, w.st, k, nf, fw, s)) != FE_OK) return st;
@@ -489,12 +545,13 @@ fe_status minres_core(const Mesh& m, const double* v, const T* Psi, const double
     }
   }
   if ((st = flush(true)) != FE_OK) return st;
-  if ((st = project_out(Psi, k0, Q, k0, nf, f32, w.pw, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, kpsi, Q, k0, nf, f32, w.pw, s)) != FE_OK) return st;
   return FE_OK;
 }
 
-// FP64 true residual R = B - P (H - eps) P Q and its column norms rr (device).
-fe_status true_residual(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k,
+// FP64 true residual R = B - P (H - eps) P Q of k columns and their norms rr (device); Psi has
+// kpsi columns.
+fe_status true_residual(const Mesh& m, const double* v, const double* Psi, int kpsi, const double* eps_h, int k,
                         const double* B, const double* Q, double* R, double* rr, double* pw, hipStream_t s) {
   ApplyArgs aa{};
   aa.v = v;
@@ -506,7 +563,7 @@ fe_status true_residual(const Mesh& m, const double* v, const double* Psi, const
   aa.Y = R;
   fe_status st;
   if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;
-  if ((st = project_out(Psi, k, R, k, m.nf, false, pw, s)) != FE_OK) return st;
+  if ((st = project_out(Psi, kpsi, R, k, m.nf, false, pw, s)) != FE_OK) return st;
   if ((st = k_sub_from(B, R, (int64_t)m.nf * k, s)) != FE_OK) return st;
   return coldot(R, R, k, m.nf, k, false, rr, pw, s);
 }
@@ -828,7 +885,7 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
     case FE_OP_CHEB_FILTER: return filter_work(m, nv, prec);
     case FE_OP_RAYLEIGH_RITZ: rr_layout(bp, m, nv, nv); return bp.off;
     case FE_OP_EIGENSOLVE: eig_layout(bp, m, nv, nv, prec); return bp.off;
-    case FE_OP_ADJOINT_SOLVE: mr_layout(bp, m, nv, prec); return bp.off;
+    case FE_OP_ADJOINT_SOLVE: adjoint_layout(bp, m, nv, prec); return bp.off;
     case FE_OP_ADJOINT_DEFLATED: {  // nv = nocc + nbuf: a bound for every split of nv
       if (nv > 64) return 0;
       double *u, *pw;
@@ -989,7 +1046,7 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
                     void* stream) {
   if (check_mesh(mesh) != FE_OK) return FE_EINVAL;
   if (!Psi || !occ_h) return fail(FE_EINVAL, "loss_grad: Psi and occ_h are required");
-  if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "loss_grad: nocc must be in [1, 64]");
+  if (nocc < 1 || nocc > kMaxShiftCols) return fail(FE_EINVAL, "loss_grad: nocc must be in [1, 256]");
   const Mesh& m = mesh->m;
   const bool needs_work = !Q || (loss_h && rho && rho_data);
   if (needs_work && !work) return fail(FE_EINVAL, "loss_grad: work is NULL");
@@ -1006,9 +1063,9 @@ fe_status loss_grad(fe_mesh mesh, const double* Psi, const double* occ_h, int no
 // the Euclidean bar ||b - A q|| <= 2 tol ||b|| on every column: columns above it are refined
 // (at most three rounds). maxit bounds the whole solve: the first solve and the refinement
 // rounds draw on one budget, counted in iterations of the slowest column.
-fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const double* eps_h, int k, const double* B,
-                      double* Q, double tol, int maxit, int* iters_h, double* relres_h, MRWork& w, Deflation* df,
-                      const char* name, hipStream_t s) {
+fe_status adjoint_f64(const Mesh& m, const double* v, const ProjSet<double>& ps, const double* eps_h, int k,
+                      const double* B, double* Q, double tol, int maxit, int* iters_h, double* relres_h, MRWork& w,
+                      Deflation* df, const char* name, hipStream_t s) {
   fe_status st;
   std::vector<double> its, active, rr(k), bb(k);
   bool conv = true;
@@ -1016,13 +1073,13 @@ fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const d
   // deflated directions by 1 / (theta - eps) and so understates the Euclidean one (by 6 to 17
   // times on the model molecules); refinement below covers what this factor misses
   const double tol1 = df ? tol / 6.0 : tol;
-  if ((st = minres_core<double>(m, v, Psi, eps_h, k, B, Q, tol1, maxit, w, its, active, s, df)) != FE_OK) return st;
+  if ((st = minres_core<double>(m, v, ps, eps_h, k, B, Q, tol1, maxit, w, its, active, s, df)) != FE_OK) return st;
   int used = 0;
   for (int j = 0; j < k; ++j) {
     if (active[j] > 0.0) conv = false;
     used = std::max(used, (int)its[j]);
   }
-  if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
+  if ((st = true_residual(m, v, ps.Psi, ps.kpsi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
   if ((st = coldot(B, B, k, m.nf, k, false, w.bnorm, w.pw, s)) != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
   INVDFT_HIP(hipMemcpyAsync(bb.data(), w.bnorm, k * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1045,7 +1102,7 @@ fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const d
     if ((st = rotate(w.rb, k, m.nf, k, w.mask, k, w.rb, k, s)) != FE_OK) return st;
     const double tol2 = std::min(0.5, std::max(1e-14, 0.5 * tol * need));
     std::vector<double> its2, act2;
-    if ((st = minres_core<double>(m, v, Psi, eps_h, k, w.rb, w.dq, tol2, maxit - used, w, its2, act2, s, df)) !=
+    if ((st = minres_core<double>(m, v, ps, eps_h, k, w.rb, w.dq, tol2, maxit - used, w, its2, act2, s, df)) !=
         FE_OK)
       return st;
     int mx = 0;
@@ -1056,7 +1113,7 @@ fe_status adjoint_f64(const Mesh& m, const double* v, const double* Psi, const d
     }
     used += mx;
     if ((st = axpby(1.0, w.dq, 1.0, Q, (int64_t)m.nf * k, s)) != FE_OK) return st;
-    if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
+    if ((st = true_residual(m, v, ps.Psi, ps.kpsi, eps_h, k, B, Q, w.rb, w.d1, w.pw, s)) != FE_OK) return st;
     INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
     INVDFT_HIP(hipStreamSynchronize(s));
   }
@@ -1106,7 +1163,8 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
     if ((st = project_out(Psi, nocc, Uc, nbuf, m.nf, false, w.pw, s)) != FE_OK) return st;
   if ((st = defl_pack(Psi, nocc, Uc, nbuf, df.V, m.nf, s)) != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(df.theta, theta_h, nbuf * sizeof(double), hipMemcpyHostToDevice, s));
-  return adjoint_f64(m, v, Psi, eps_h, nocc, B, Q, tol, maxit, iters_h, relres_h, w, &df, "adjoint_solve_deflated", s);
+  return adjoint_f64(m, v, proj_whole(Psi, nocc), eps_h, nocc, B, Q, tol, maxit, iters_h, relres_h, w, &df,
+                     "adjoint_solve_deflated", s);
 }
 
 fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const double* eps_h, int nocc,
@@ -1116,21 +1174,42 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
   if (!v || !Psi || !eps_h || !B || !Q || !work) return fail(FE_EINVAL, "adjoint_solve: NULL argument");
   if (!aligned16(Psi) || !aligned16(B) || !aligned16(Q) || !aligned16(work))
     return fail(FE_EINVAL, "adjoint_solve: Psi, B, Q and work must be 16-byte aligned");
-  if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "adjoint_solve: nocc must be in [1, 64]");
+  if (nocc < 1 || nocc > kMaxShiftCols) return fail(FE_EINVAL, "adjoint_solve: nocc must be in [1, 256]");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve: tol > 0 and maxit >= 1 required");
   if (prec != FE_F64 && prec != FE_F32) return fail(FE_EINVAL, "adjoint_solve: unsupported precision");
+  if (prec == FE_F32 && nocc > 64) return fail(FE_EINVAL, "adjoint_solve: FE_F32 takes at most 64 orbitals");
   const Mesh& m = mesh->m;
   hipStream_t s = S(stream);
   Bump bp(work);
-  MRWork w = mr_layout(bp, m, nocc, prec);
+  MRWork w = adjoint_layout(bp, m, nocc, prec);
   const int k = nocc;
   const size_t blk = (size_t)m.nf * k;
   fe_status st;
   if ((st = k_dinv(m, w.dinv, s)) != FE_OK) return st;
   std::vector<double> its, active, total_its(k, 0.0), rr(k), bb(k);
   bool conv = true;
-  if (prec == FE_F64) {
-    return adjoint_f64(m, v, Psi, eps_h, k, B, Q, tol, maxit, iters_h, relres_h, w, nullptr, "adjoint_solve", s);
+  if (prec == FE_F64 && k <= 64) {
+    return adjoint_f64(m, v, proj_whole(Psi, k), eps_h, k, B, Q, tol, maxit, iters_h, relres_h, w, nullptr,
+                       "adjoint_solve", s);
+  } else if (prec == FE_F64) {
+    // More than 64 orbitals: the shifts in groups of at most 64 columns, each solved against all
+    // of Psi. The fused passes take the first 64 orbitals (a block of their own, 64-column rows);
+    // the others are projected by separate sweeps.
+    const size_t es = sizeof(double);
+    INVDFT_HIP(hipMemcpy2DAsync(w.Pf, 64 * es, Psi, k * es, 64 * es, m.nf, hipMemcpyDeviceToDevice, s));
+    const ProjSet<double> ps{Psi, k, w.Pf, 64, Psi + 64, k - 64};
+    std::string nc_msg;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+      const int kc = std::min(64, k - c0);
+      INVDFT_HIP(hipMemcpy2DAsync(w.Bg, kc * es, B + c0, k * es, kc * es, m.nf, hipMemcpyDeviceToDevice, s));
+      st = adjoint_f64(m, v, ps, eps_h + c0, kc, w.Bg, w.Qg, tol, maxit, iters_h ? iters_h + c0 : nullptr,
+                       relres_h ? relres_h + c0 : nullptr, w, nullptr, "adjoint_solve", s);
+      if (st == FE_ENOCONV && nc_msg.empty()) nc_msg = g_err;
+      if (st != FE_OK && st != FE_ENOCONV) return st;
+      INVDFT_HIP(hipMemcpy2DAsync(Q + c0, k * es, w.Qg, kc * es, kc * es, m.nf, hipMemcpyDeviceToDevice, s));
+    }
+    INVDFT_HIP(hipStreamSynchronize(s));
+    return nc_msg.empty() ? FE_OK : fail(FE_ENOCONV, nc_msg);
   } else {
     // FP32 MINRES inner solves with FP64 iterative refinement: q += d, (H - eps) d = r in FP32,
     // r = b - (H - eps) q in FP64, until every column reaches tol.
@@ -1159,8 +1238,8 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
       if ((st = k_mask_cols(Rf, w.d1, w.bnorm, tol, k, m.nf, s)) != FE_OK) return st;
       // the FP32 correction is stored in the (larger) FP64 scratch block Y64
       float* Dsol = reinterpret_cast<float*>(w.Y64);
-      if ((st = minres_core<float>(m, v, w.Psif, eps_h, k, Rf, Dsol, tol_inner, maxit - used, w, its, active, s)) !=
-          FE_OK)
+      if ((st = minres_core<float>(m, v, proj_whole<float>(w.Psif, k), eps_h, k, Rf, Dsol, tol_inner, maxit - used, w,
+                                   its, active, s)) != FE_OK)
         return st;
       int mx = 0;
       for (int j = 0; j < k; ++j) {
@@ -1170,7 +1249,7 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
       used += std::max(mx, 1);
       if ((st = k_add_f32(Dsol, Q, blk, s)) != FE_OK) return st;
       if ((st = project_out(Psi, k, Q, k, m.nf, false, w.pw, s)) != FE_OK) return st;
-      if ((st = true_residual(m, v, Psi, eps_h, k, B, Q, w.R64, w.d1, w.pw, s)) != FE_OK) return st;
+      if ((st = true_residual(m, v, Psi, k, eps_h, k, B, Q, w.R64, w.d1, w.pw, s)) != FE_OK) return st;
       INVDFT_HIP(hipMemcpyAsync(rr.data(), w.d1, k * sizeof(double), hipMemcpyDeviceToHost, s));
       INVDFT_HIP(hipStreamSynchronize(s));
     }
@@ -1205,7 +1284,7 @@ fe_status fe_dot(const double* x, const double* y, int64_t n, double* out_h, voi
 }
 
 fe_status fe_axpby(double alpha, const double* x, double beta, double* y, int64_t n, void* stream) {
-  if (!x || !y || n < 0) return fail(FE_EINVAL, "fe_axpby: bad argument");
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(FE_EINVAL, "fe_axpby: bad argument");
   return axpby(alpha, x, beta, y, n, S(stream));
 }
 
@@ -1213,6 +1292,10 @@ fe_status fe_apply_timing(int enable) { return apply_timing(enable); }
 
 fe_status fe_apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns) {
   return apply_timing_read(prec, launches, ms, bytes, columns);
+}
+
+fe_status fe_sweep_timing_read(int pass, int64_t* launches, double* ms, double* bytes, double* columns) {
+  return sweep_timing_read(pass, launches, ms, bytes, columns);
 }
 
 }  // extern "C"

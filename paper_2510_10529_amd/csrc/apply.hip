@@ -29,7 +29,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <vector>
 
 #include "internal.h"
 #include "ref_tables.h"
@@ -1006,83 +1005,21 @@ fe_status launch_p(const Mesh& m, KParams& prm, hipStream_t s) {
 
 }  // namespace
 
-// ---- optional per-launch timing of the apply (a measurement aid)
-namespace {
-struct TimedLaunch {
-  hipEvent_t start, stop;
-  int prec;
-  double bytes;
-  double cols;
-};
-struct ApplyTiming {
-  bool on = false;
-  std::vector<TimedLaunch> rec;     // launches of the current measurement
-  std::vector<hipEvent_t> spare;    // events of earlier measurements, reused
-  hipEvent_t take() {
-    hipEvent_t e = nullptr;
-    if (!spare.empty()) {
-      e = spare.back();
-      spare.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-      e = nullptr;
-    }
-    return e;
-  }
-  void clear() {
-    for (auto& t : rec) {
-      spare.push_back(t.start);
-      spare.push_back(t.stop);
-    }
-    rec.clear();
-  }
-};
-ApplyTiming g_timing;
-}  // namespace
-
-fe_status apply_timing(int enable) {
-  if (enable) g_timing.clear();
-  g_timing.on = enable != 0;
-  return FE_OK;
-}
-
-fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns) {
-  if (prec != FE_F64 && prec != FE_F32 && prec != FE_BF16)
-    return fail(FE_EINVAL, "fe_apply_timing_read: prec must be FE_F64, FE_F32 or FE_BF16");
-  int64_t n = 0;
-  double t = 0.0, b = 0.0, cl = 0.0;
-  for (auto& r : g_timing.rec) {
-    if (r.prec != (int)prec) continue;
-    INVDFT_HIP(hipEventSynchronize(r.stop));
-    float e = 0.0f;
-    INVDFT_HIP(hipEventElapsedTime(&e, r.start, r.stop));
-    ++n;
-    t += e;
-    b += r.bytes;
-    cl += r.cols;
-  }
-  if (launches) *launches = n;
-  if (ms) *ms = t;
-  if (bytes) *bytes = b;
-  if (columns) *columns = cl;
-  return FE_OK;
-}
-
+// ---- the apply, optionally timed (launch timing is a measurement aid)
 static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
 
 fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s) {
-  if (!g_timing.on || m.nf == 0) return launch_apply_untimed(m, a, prec, s);
+  if (m.nf == 0) return launch_apply_untimed(m, a, prec, s);
   // algorithmic bytes: X read, Y written, Z read when given (the Chebyshev term), v read
   const double blocks = a.Z ? 3.0 : 2.0;
-  TimedLaunch t{g_timing.take(), g_timing.take(), (int)prec,
-                (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : prec == FE_F32 ? 4.0 : 2.0) + 8.0) +
-                    (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0),
-                (double)a.nv};
-  if (!t.start || !t.stop) return fail(FE_EDEVICE, "ks_apply timing: hipEventCreate failed");
-  INVDFT_HIP(hipEventRecord(t.start, s));
-  const fe_status st = launch_apply_untimed(m, a, prec, s);
-  INVDFT_HIP(hipEventRecord(t.stop, s));
-  g_timing.rec.push_back(t);
-  return st;
+  const double bytes = (double)m.nf * (blocks * a.nv * (prec == FE_F64 ? 8.0 : prec == FE_F32 ? 4.0 : 2.0) + 8.0) +
+                       (m.mapped ? (double)mapped_matrix_bytes(m, prec) : 0.0);
+  int slot;
+  fe_status st = timed_begin((int)prec, bytes, (double)a.nv, s, &slot);
+  if (st != FE_OK) return st;
+  st = launch_apply_untimed(m, a, prec, s);
+  const fe_status st2 = timed_end(slot, s);
+  return st != FE_OK ? st : st2;
 }
 
 static fe_status launch_apply_untimed(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s) {

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "internal.h"
 
@@ -143,16 +144,17 @@ int gram_blocks(long long N) {
   return (int)std::max<long long>(1, std::min<long long>(b, 1024));
 }
 
-// out = alpha * (A C) + beta * Xin  over N rows; A: N x nin (lda), C: nin x nout (row-major, device),
-// Xin/out: N x nout (ldo). Each wave owns 16 rows and all nout (<= 64) columns; out may alias Xin.
+// out = alpha * (A C) + beta * Xin  over N rows; A: N x nin (lda), C: nin x nout (row stride ldc,
+// device), Xin/out: N x nout (ldo). Each wave owns 16 rows and all nout (<= 64) columns, nin <= 64;
+// out may alias Xin, and A too: a wave reads all of its rows of A before it writes them.
 template <typename T>
 __global__ __launch_bounds__(256) void rotate_kernel(const T* A, int lda, long long N, int nin,
-                                                     const double* __restrict__ C, int nout, double alpha,
+                                                     const double* __restrict__ C, int ldc, int nout, double alpha,
                                                      double beta, const T* Xin, T* out, int ldo) {
   __shared__ double sC[64 * 64];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int k = e / 64, j = e % 64;
-    sC[e] = (k < nin && j < nout) ? C[k * nout + j] : 0.0;
+    sC[e] = (k < nin && j < nout) ? C[(long long)k * ldc + j] : 0.0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -339,6 +341,26 @@ __global__ void axpby_kernel(double alpha, const double* __restrict__ x, double 
     y[i] = alpha * x[i] + beta * y[i];
 }
 
+// The same on 16-byte pieces (both arrays 16-byte aligned), four pieces of each array in flight
+// per thread: the loads of an iteration are issued before any of its stores.
+typedef double d2v __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void axpby2_kernel(double alpha, const d2v* __restrict__ x, double beta,
+                                                     d2v* __restrict__ y, long long n2) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    d2v a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = x[i + u * stride];
+      b[u] = y[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[i + u * stride] = alpha * a[u] + beta * b[u];
+  }
+  for (; i < n2; i += stride) y[i] = alpha * x[i] + beta * y[i];
+}
+
 __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] = val;
@@ -403,26 +425,51 @@ fe_status rotate_add(const double* X, int ldx, int64_t N, int nin, const double*
   return rotate_axpy(X, ldx, N, nin, C, nout, 1.0, Y, ldy, s);
 }
 
+// out = alpha A C + beta Xin for any widths: 64 x 64 tiles of C, one launch each, accumulating
+// over the input tiles into out (the first with beta Xin, the rest with out itself). Above 64
+// columns in or out, out must not overlap A.
+template <typename T>
+fe_status rotate_tiled(const T* A, int lda, int64_t N, int nin, const double* C, int ldc, int nout, double alpha,
+                       double beta, const T* Xin, T* out, int ldo, hipStream_t s) {
+  if (N <= 0 || nin <= 0 || nout <= 0) return FE_OK;
+  const unsigned grid = (unsigned)((N + 63) / 64);
+  for (int j0 = 0; j0 < nout; j0 += 64) {
+    const int nj = std::min(64, nout - j0);
+    for (int k0 = 0; k0 < nin; k0 += 64) {
+      const int nk = std::min(64, nin - k0);
+      const bool first = k0 == 0;
+      hipLaunchKernelGGL(rotate_kernel<T>, dim3(grid), dim3(256), 0, s, A + k0, lda, (long long)N, nk,
+                         C + (long long)k0 * ldc + j0, ldc, nj, alpha, first ? beta : 1.0,
+                         first ? (Xin ? Xin + j0 : nullptr) : out + j0, out + j0, ldo);
+      INVDFT_HIP(hipGetLastError());
+    }
+  }
+  return FE_OK;
+}
+
+// do the column ranges of two N-row blocks share memory?
+bool blocks_overlap(const void* a, int lda, int na, const void* b, int ldb, int nb, int64_t N, size_t es) {
+  const char* a0 = static_cast<const char*>(a);
+  const char* b0 = static_cast<const char*>(b);
+  const char* a1 = a0 + ((size_t)(N - 1) * lda + na) * es;
+  const char* b1 = b0 + ((size_t)(N - 1) * ldb + nb) * es;
+  return a0 < b1 && b0 < a1;
+}
+
 fe_status rotate_axpy(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double alpha, double* Y,
                       int ldy, hipStream_t s) {
-  if (nin > 64 || nout > 64) return fail(FE_EINVAL, "rotate: blocks wider than 64 columns are not supported");
   if (N <= 0) return FE_OK;
-  const unsigned grid = (unsigned)((N + 63) / 64);
-  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, alpha,
-                     1.0, (const double*)Y, Y, ldy);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
+  if ((nin > 64 || nout > 64) && blocks_overlap(X, ldx, nin, Y, ldy, nout, N, sizeof(double)))
+    return fail(FE_EINVAL, "rotate: above 64 columns the output must not overlap the input");
+  return rotate_tiled<double>(X, ldx, N, nin, C, nout, nout, alpha, 1.0, Y, Y, ldy, s);
 }
 
 fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* out, int ldo,
                  hipStream_t s) {
-  if (nin > 64 || nout > 64) return fail(FE_EINVAL, "rotate: blocks wider than 64 columns are not supported");
   if (N <= 0) return FE_OK;
-  const unsigned grid = (unsigned)((N + 63) / 64);
-  hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, X, ldx, (long long)N, nin, C, nout, 1.0, 0.0,
-                     (const double*)nullptr, out, ldo);
-  INVDFT_HIP(hipGetLastError());
-  return FE_OK;
+  if ((nin > 64 || nout > 64) && blocks_overlap(X, ldx, nin, out, ldo, nout, N, sizeof(double)))
+    return fail(FE_EINVAL, "rotate: above 64 columns the output must not overlap the input");
+  return rotate_tiled<double>(X, ldx, N, nin, C, nout, nout, 1.0, 0.0, nullptr, out, ldo, s);
 }
 
 size_t coldot_work_bytes(int64_t N, int nv) { return (size_t)gram_blocks(N) * nv * sizeof(double); }
@@ -522,8 +569,22 @@ fe_status cast_cols_to_f64(const float* src, double* dst, int64_t nrow, int ld, 
 }
 
 fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(axpby_kernel, dim3(stream_grid(n)), dim3(256), 0, s, alpha, x, beta, y, (long long)n);
+  if (n <= 0) return FE_OK;
+  const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0 && n >= 2;
+  if (!vec) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(stream_grid(n)), dim3(256), 0, s, alpha, x, beta, y, (long long)n);
+    INVDFT_HIP(hipGetLastError());
+    return FE_OK;
+  }
+  const long long n2 = n / 2;
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((n2 + 255) / 256, 2048));
+  hipLaunchKernelGGL(axpby2_kernel, dim3(grid), dim3(256), 0, s, alpha, reinterpret_cast<const d2v*>(x), beta,
+                     reinterpret_cast<d2v*>(y), n2);
   INVDFT_HIP(hipGetLastError());
+  if (n % 2) {  // the last element of an odd length
+    hipLaunchKernelGGL(axpby_kernel, dim3(1), dim3(64), 0, s, alpha, x + n - 1, beta, y + n - 1, 1LL);
+    INVDFT_HIP(hipGetLastError());
+  }
   return FE_OK;
 }
 
@@ -534,27 +595,45 @@ fe_status fill(double* y, double val, int64_t n, hipStream_t s) {
 }
 
 size_t project_work_bytes(int64_t N, int k, int nv) {
-  return gram_work_bytes(N, k, nv) + (size_t)k * nv * sizeof(double) + 256;
+  // a group of at most 64 columns at a time: its k x 64 Gram block and one tile's partials
+  const int cw = std::min(nv, 64);
+  return gram_work_bytes(N, std::min(k, 64), cw) + (((size_t)k * cw * sizeof(double) + 255) / 256) * 256 + 256;
 }
 
-fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s) {
-  if (k > 64 || nv > 64) return fail(FE_EINVAL, "projection: blocks wider than 64 columns are not supported");
+// X <- X - Psi (Psi^T X), one group of at most 64 columns of X at a time: the group's Gram
+// blocks with every 64-column segment of Psi first, then its update (classical block
+// projection, as for a single tile).
+template <typename T>
+fe_status project_out_t(const T* Psi, int ldp, int k, T* X, int nv, int64_t N, void* work, hipStream_t s) {
+  const int cwmax = std::min(nv, 64);
   char* w = static_cast<char*>(work);
   double* G = reinterpret_cast<double*>(w);
-  void* gw = w + (((size_t)k * nv * sizeof(double) + 255) / 256) * 256;
-  fe_status st = gram(Psi, k, X, nv, N, k, nv, f32, G, gw, s);
-  if (st != FE_OK) return st;
-  const unsigned grid = (unsigned)((N + 63) / 64);
-  if (f32)
-    hipLaunchKernelGGL(rotate_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(Psi), k,
-                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const float*>(X), static_cast<float*>(X), nv);
-  else
-    hipLaunchKernelGGL(rotate_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(Psi), k,
-                       (long long)N, k, G, nv, -1.0, 1.0, static_cast<const double*>(X), static_cast<double*>(X), nv);
-  INVDFT_HIP(hipGetLastError());
+  void* gw = w + (((size_t)k * cwmax * sizeof(double) + 255) / 256) * 256;
+  const bool f32 = sizeof(T) == sizeof(float);
+  fe_status st;
+  for (int c0 = 0; c0 < nv; c0 += 64) {
+    const int cw = std::min(64, nv - c0);
+    for (int s0 = 0; s0 < k; s0 += 64) {
+      const int kw = std::min(64, k - s0);
+      if ((st = gram(Psi + s0, ldp, X + c0, nv, N, kw, cw, f32, G + (size_t)s0 * cw, gw, s)) != FE_OK) return st;
+    }
+    if ((st = rotate_tiled<T>(Psi, ldp, N, k, G, cw, cw, -1.0, 1.0, X + c0, X + c0, nv, s)) != FE_OK) return st;
+  }
   return FE_OK;
 }
 
+fe_status project_out_ld(const void* Psi, int ldp, int k, void* X, int nv, int64_t N, bool f32, void* work,
+                         hipStream_t s) {
+  if (k < 1 || nv < 1 || N <= 0) return FE_OK;
+  if (ldp < k) return fail(FE_EINVAL, "projection: the row pitch of Psi is below its width");
+  if (f32)
+    return project_out_t<float>(static_cast<const float*>(Psi), ldp, k, static_cast<float*>(X), nv, N, work, s);
+  return project_out_t<double>(static_cast<const double*>(Psi), ldp, k, static_cast<double*>(X), nv, N, work, s);
+}
+
+fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s) {
+  return project_out_ld(Psi, k, k, X, nv, N, f32, work, s);
+}
 
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3(stream_grid(n)), dim3(256), 0, s, y, val, (long long)n);

@@ -94,15 +94,23 @@ fe_status launch_apply(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStrea
 fe_status mapped_setup(Mesh& m, double amp);
 fe_status launch_apply_mapped(const Mesh& m, const ApplyArgs& a, fe_prec prec, hipStream_t s);
 size_t mapped_matrix_bytes(const Mesh& m, fe_prec prec);
+// Launch timing (a measurement aid): while enabled, timed_begin records a start event on s and
+// returns a slot (-1 when timing is off), timed_end records the stop event. kind is an fe_prec for
+// operator applies and kTimedSweep + pass (0, 1, 2 = A, B, C) for the MINRES row sweeps.
+constexpr int kTimedSweep = 16;
 fe_status apply_timing(int enable);
 fe_status apply_timing_read(fe_prec prec, int64_t* launches, double* ms, double* bytes, double* columns);
+fe_status sweep_timing_read(int pass, int64_t* launches, double* ms, double* bytes, double* columns);
+fe_status timed_begin(int kind, double bytes, double cols, hipStream_t s, int* slot);
+fe_status timed_end(int slot, hipStream_t s);
 
 // Block operations (FP64 reductions; T = double or float storage).
 // Gram: out (nx x ny, row-major, FP64 device) = X^T Y over the first N rows.
 size_t gram_work_bytes(int64_t N, int nx, int ny);
 fe_status gram(const void* X, int ldx, const void* Y, int ldy, int64_t N, int nx, int ny, bool f32,
                double* out, void* work, hipStream_t s);
-// out[a, j] = sum_k X[a, k] C[k, j] (C FP64 device, nin x nout, row-major); out may equal X.
+// out[a, j] = sum_k X[a, k] C[k, j] (C FP64 device, nin x nout, row-major); out may equal X up to
+// 64 columns in and out (wider blocks are rotated in 64 x 64 tiles and out must not overlap X).
 fe_status rotate(const double* X, int ldx, int64_t N, int nin, const double* C, int nout, double* out,
                  int ldo, hipStream_t s);
 // Column-wise dot products d_j = sum_a X[a,j] Y[a,j] (FP64 result, device array nv).
@@ -141,10 +149,14 @@ fe_status cast_cols_to_f64(const float* src, double* dst, int64_t nrow, int ld, 
 fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s);
 fe_status fill(double* y, double val, int64_t n, hipStream_t s);
 
-// Projection X <- X - Psi (Psi^T X) (Psi: N x k, ld k; X: N x nv, ld nv). work: gram work + k*nv.
+// Projection X <- X - Psi (Psi^T X) (Psi: N x k, ld k; X: N x nv, ld nv), any widths, in groups
+// of at most 64 columns of X. work: project_work_bytes(N, k, nv).
 size_t project_work_bytes(int64_t N, int k, int nv);
 // f32: Psi and X are float blocks (products accumulated in FP64).
 fe_status project_out(const void* Psi, int k, void* X, int nv, int64_t N, bool f32, void* work, hipStream_t s);
+// The same with Psi's row pitch ldp >= k (Psi a column range of a wider block).
+fe_status project_out_ld(const void* Psi, int ldp, int k, void* X, int nv, int64_t N, bool f32, void* work,
+                         hipStream_t s);
 // X <- X - Psi G with a given G (k x nv, FP64 device).
 fe_status fill_f32(float* y, float val, int64_t n, hipStream_t s);
 fe_status copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s);

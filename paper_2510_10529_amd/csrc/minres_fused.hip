@@ -520,13 +520,15 @@ fe_status minres_pass_a(const T* Psi, int k0, const T* Y, const T* Z, const T* R
   if ((st = check_widths(k0, k)) != FE_OK) return st;
   if (N <= 0) return FE_OK;
   const int nb = fused_blocks(N);
+  int slot;  // algorithmic bytes: Psi, Y, Z, R1 read
+  if ((st = timed_begin(kTimedSweep + 0, (double)N * sizeof(T) * (k0 + 3.0 * k), k, s, &slot)) != FE_OK) return st;
   hipLaunchKernelGGL(pass_a_kernel<T>, dim3(nb), dim3(kThreads), 0, s, Psi, k0, Y, Z, R1, k, (long long)N, fw.partG,
                      fw.partD);
   INVDFT_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3((k0 * k + 2 * k + 3) / 4), dim3(256), 0, s, fw.partG, fw.partD, nb, k0, k, 2,
                      fw.G, fw.d1);
   INVDFT_HIP(hipGetLastError());
-  return FE_OK;
+  return timed_end(slot, s);
 }
 
 template <typename T>
@@ -536,13 +538,16 @@ fe_status minres_pass_b(const T* Psi, int k0, T* Y, T* R1, const T* R2, const do
   if ((stt = check_widths(k0, k)) != FE_OK) return stt;
   if (N <= 0) return FE_OK;
   const int nb = fused_blocks(N);
+  int slot;  // algorithmic bytes: Psi, Y, R1, R2 and the diagonal read, R1 and Y written
+  if ((stt = timed_begin(kTimedSweep + 1, (double)N * (sizeof(T) * (k0 + 5.0 * k) + 8.0), k, s, &slot)) != FE_OK)
+    return stt;
   hipLaunchKernelGGL(pass_b_kernel<T>, dim3(nb), dim3(kThreads), 0, s, Psi, k0, fw.G, Y, R1, R2, st, dinv, k,
                      (long long)N, fw.partG, fw.partD);
   INVDFT_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3((k0 * k + k + 3) / 4), dim3(256), 0, s, fw.partG, fw.partD, nb, k0, k, 1,
                      fw.G2, fw.d);
   INVDFT_HIP(hipGetLastError());
-  return FE_OK;
+  return timed_end(slot, s);
 }
 
 template <typename T>
@@ -551,10 +556,12 @@ fe_status minres_pass_c(const T* Psi, int k0, T* U, const T* Zold, T* W1, const 
   fe_status stt;
   if ((stt = check_widths(k0, k)) != FE_OK) return stt;
   if (N <= 0) return FE_OK;
+  int slot;  // algorithmic bytes: Psi, U, Zold, W1, W2, X read, U, W1, X written
+  if ((stt = timed_begin(kTimedSweep + 2, (double)N * sizeof(T) * (k0 + 8.0 * k), k, s, &slot)) != FE_OK) return stt;
   hipLaunchKernelGGL(pass_c_kernel<T>, dim3(fused_blocks(N)), dim3(kThreads), 0, s, Psi, k0, fw.G2, U, Zold, W1, W2,
                      X, st, k, (long long)N);
   INVDFT_HIP(hipGetLastError());
-  return FE_OK;
+  return timed_end(slot, s);
 }
 
 template fe_status minres_pass_a<double>(const double*, int, const double*, const double*, const double*, int, int64_t,

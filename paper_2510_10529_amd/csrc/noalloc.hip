@@ -10,8 +10,9 @@
 namespace invdft {
 namespace {
 
-// 1025 doubles of loss partials + 1024 blocks x one 64 x 64 Gram tile + the 64 x 64 product,
-// each rounded to 256 bytes: 33,595,904 bytes at the largest nocc (64) and mesh.
+// 1025 doubles of loss partials + 1024 blocks x one 64 x 64 Gram tile + the nocc x 64 Gram block
+// of one column group of B, each rounded to 256 bytes: 33,595,904 bytes at nocc = 64 and
+// 33,694,208 at the largest nocc (256), on the largest mesh.
 constexpr size_t kScratchBytes = 34u << 20;
 constexpr int kMaxDevices = 64;
 
@@ -50,7 +51,7 @@ extern "C" fe_status loss_grad_noalloc(fe_mesh mesh, const double* Psi, const do
   const Mesh* m = mesh_tables(mesh);
   if (!m) return fail(FE_EINVAL, "mesh handle is NULL");
   if (!Psi || !occ_h) return fail(FE_EINVAL, "loss_grad_noalloc: Psi and occ_h are required");
-  if (nocc < 1 || nocc > 64) return fail(FE_EINVAL, "loss_grad_noalloc: nocc must be in [1, 64]");
+  if (nocc < 1 || nocc > kMaxShiftCols) return fail(FE_EINVAL, "loss_grad_noalloc: nocc must be in [1, 256]");
   if (!Q && !rho) return fail(FE_EINVAL, "loss_grad_noalloc: phase 1 needs rho (no density buffer of its own)");
   const size_t need = loss_grad_scratch_bytes(m->nf, nocc);
   if (need > kScratchBytes)

@@ -118,7 +118,7 @@ extern "C" fe_status adjoint_along_psi(fe_mesh mesh, const double* Psi, int n, c
   if (fe_mesh_info(mesh, &nf, nullptr, nullptr, nullptr) != FE_OK) return FE_EINVAL;
   if (!Psi || !eps_h || !rho || !rho_data || !Q || !work)
     return fail(FE_EINVAL, "adjoint_along_psi: NULL argument");
-  if (n < 1 || n > 64) return fail(FE_EINVAL, "adjoint_along_psi: n must be in [1, 64]");
+  if (n < 1 || n > kMaxShiftCols) return fail(FE_EINVAL, "adjoint_along_psi: n must be in [1, 256]");
   if (!(kT > 0.0) || !(smax > 0.0)) return fail(FE_EINVAL, "adjoint_along_psi: kT > 0 and smax > 0 required");
   if (((reinterpret_cast<uintptr_t>(Psi) | reinterpret_cast<uintptr_t>(Q) | reinterpret_cast<uintptr_t>(work)) &
        15u) != 0)

@@ -108,8 +108,12 @@ class InverseProblem:
         if o.deflate > 0:
             if o.adjoint_prec != "f64":
                 raise ValueError("the deflated adjoint solve is FP64 only")
-            self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED,
-                                                           min(64, self.nocc + o.deflate), "f64"), dev)
+            # deflation while the orbitals and the deflation vectors fit 64 columns; the plain
+            # solve (wider blocks, or no deflation vector clearing the shifts) in the same buffer
+            need = mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, "f64")
+            if self.nocc < 64:
+                need = max(need, mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED, min(64, self.nocc + o.deflate), "f64"))
+            self.work_adj = api._work(need, dev)
         else:
             self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
         self.work_lg = api._work(mesh.workspace_bytes(L.FE_OP_LOSS_GRAD, self.nocc), dev)

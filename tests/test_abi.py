@@ -67,6 +67,8 @@ def test_argument_checks_without_gpu():
     assert lib.fe_mesh_destroy(null) == _lib.FE_OK
     out = C.c_double()
     assert lib.fe_dot(None, None, 10, C.byref(out), None, None) == _lib.FE_EINVAL
+    assert lib.fe_axpby(C.c_double(1.0), None, C.c_double(1.0), None, 5, None) == _lib.FE_EINVAL
+    assert lib.fe_axpby(C.c_double(1.0), None, C.c_double(1.0), None, 0, None) == _lib.FE_OK   # empty: nothing
     # apply timing: an empty record reads back as zero launches, a bad precision is rejected
     n, ms, b = C.c_int64(7), C.c_double(1.0), C.c_double(1.0)
     assert lib.fe_apply_timing(1) == _lib.FE_OK
@@ -74,6 +76,9 @@ def test_argument_checks_without_gpu():
     assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
     assert lib.fe_apply_timing(0) == _lib.FE_OK
     assert lib.fe_apply_timing_read(3, None, None, None, None) == _lib.FE_EINVAL     # no such precision
+    assert lib.fe_sweep_timing_read(0, C.byref(n), C.byref(ms), C.byref(b), None) == _lib.FE_OK
+    assert (n.value, ms.value, b.value) == (0, 0.0, 0.0)
+    assert lib.fe_sweep_timing_read(3, None, None, None, None) == _lib.FE_EINVAL      # no such pass
     assert lib.ks_apply(null, None, None, None, None, 1, 1, _lib.FE_BF16, None) == _lib.FE_EINVAL   # NULL mesh
     # finite temperature: argument checks return before any arithmetic
     eig = (C.c_double * 3)(-1.0, 0.0, 1.0)

@@ -106,3 +106,22 @@ def test_adjoint_euclidean_bar_and_budget(deflated):
     Q2, ar2 = api.adjoint_solve(m, v, Psi, eps, B, tol=tol, maxit=total - 1, **kw)
     assert ar2.status == _lib.FE_ENOCONV, ar2
     assert max(ar2.iters) <= total - 1
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 1029, (1 << 20) + 3])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_axpby_lengths_and_alignment(n, offset):
+    """fe_axpby (y = alpha x + beta y) on 16-byte pieces where both arrays allow it, element by
+    element otherwise: every length, odd tails and 8-byte-aligned views give the plain result and
+    leave the neighbouring element alone. alpha and beta are powers of two, so the products are
+    exact and the result is one rounding of the sum, with or without a fused multiply-add."""
+    from paper_2510_10529_amd import api
+    g = torch.Generator().manual_seed(n + offset)
+    xb = torch.randn(n + 1, generator=g, dtype=torch.float64)
+    yb = torch.randn(n + 1, generator=g, dtype=torch.float64)
+    want = yb.clone()
+    want[offset:offset + n] = 0.5 * xb[offset:offset + n] - 2.0 * yb[offset:offset + n]
+    xd, yd = xb.to(DEV), yb.to(DEV)
+    api.axpby(0.5, xd[offset:offset + n], -2.0, yd[offset:offset + n])
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), want.numpy())
