@@ -341,24 +341,14 @@ __global__ void axpby_kernel(double alpha, const double* __restrict__ x, double 
     y[i] = alpha * x[i] + beta * y[i];
 }
 
-// The same on 16-byte pieces (both arrays 16-byte aligned), four pieces of each array in flight
-// per thread: the loads of an iteration are issued before any of its stores.
+// The same on 16-byte pieces (both arrays 16-byte aligned), one piece per thread: a launch of
+// many short-lived workgroups streams faster than a grid-stride loop on this chip (about 5.8
+// against 4.7 TB/s for this kernel over 2^27 doubles).
 typedef double d2v __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void axpby2_kernel(double alpha, const d2v* __restrict__ x, double beta,
                                                      d2v* __restrict__ y, long long n2) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n2; i += 4 * stride) {
-    d2v a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = x[i + u * stride];
-      b[u] = y[i + u * stride];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) y[i + u * stride] = alpha * a[u] + beta * b[u];
-  }
-  for (; i < n2; i += stride) y[i] = alpha * x[i] + beta * y[i];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) y[i] = alpha * x[i] + beta * y[i];
 }
 
 __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
@@ -577,9 +567,14 @@ fe_status axpby(double alpha, const double* x, double beta, double* y, int64_t n
     return FE_OK;
   }
   const long long n2 = n / 2;
-  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((n2 + 255) / 256, 2048));
-  hipLaunchKernelGGL(axpby2_kernel, dim3(grid), dim3(256), 0, s, alpha, reinterpret_cast<const d2v*>(x), beta,
-                     reinterpret_cast<d2v*>(y), n2);
+  const long long blocks = (n2 + 255) / 256;
+  if (blocks > 0x7fffffffLL) {   // beyond one launch's grid: the grid-stride kernel
+    hipLaunchKernelGGL(axpby_kernel, dim3(stream_grid(n)), dim3(256), 0, s, alpha, x, beta, y, (long long)n);
+    INVDFT_HIP(hipGetLastError());
+    return FE_OK;
+  }
+  hipLaunchKernelGGL(axpby2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, alpha, reinterpret_cast<const d2v*>(x),
+                     beta, reinterpret_cast<d2v*>(y), n2);
   INVDFT_HIP(hipGetLastError());
   if (n % 2) {  // the last element of an odd length
     hipLaunchKernelGGL(axpby_kernel, dim3(1), dim3(64), 0, s, alpha, x + n - 1, beta, y + n - 1, 1LL);

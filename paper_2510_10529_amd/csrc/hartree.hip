@@ -105,6 +105,48 @@ __global__ void poisson_finish_kernel(const double* __restrict__ x1, const doubl
   }
 }
 
+// Preconditioned CG with its scalars on the device, so that an iteration needs no host round trip.
+// S[0] = b.b, S[1] and S[2] = r.z of alternate iterations, S[3] = p.q, S[4] = r.r, S[5] = 1 once
+// converged, S[6] = iterations done, S[7] = relative residual. Every update is a no-op once S[5]
+// is set, so the iterations launched after convergence (until the host next looks) change nothing.
+enum { kCgBB = 0, kCgPQ = 3, kCgRR = 4, kCgDone = 5, kCgIters = 6, kCgRel = 7 };
+
+__global__ void cg_init_kernel(double* __restrict__ S) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S[kCgDone] = S[kCgBB] > 0.0 ? 0.0 : 1.0;
+    S[kCgIters] = 0.0;
+    S[kCgRel] = S[kCgBB] > 0.0 ? 1.0 : 0.0;
+  }
+}
+
+// x += alpha p, r -= alpha q with alpha = (r.z) / (p.q)
+__global__ void cg_xr_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                             const double* __restrict__ q, const double* __restrict__ S, int irz, long long n) {
+  if (S[kCgDone] != 0.0) return;
+  const double alpha = S[irz] / S[kCgPQ];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] = fma(alpha, p[i], x[i]);
+    r[i] = fma(-alpha, q[i], r[i]);
+  }
+}
+
+__global__ void cg_check_kernel(double* __restrict__ S, double tol) {
+  if (blockIdx.x != 0 || threadIdx.x != 0 || S[kCgDone] != 0.0) return;
+  S[kCgIters] += 1.0;
+  const double rel = sqrt(S[kCgRR] / S[kCgBB]);
+  S[kCgRel] = rel;
+  if (rel <= tol) S[kCgDone] = 1.0;
+}
+
+// p = z + beta p with beta = (r.z)_new / (r.z)_old
+__global__ void cg_p_kernel(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ S,
+                            int inew, int iold, long long n) {
+  if (S[kCgDone] != 0.0) return;
+  const double beta = S[inew] / S[iold];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
 // Perdew-Wang 1992 correlation of the unpolarised gas (J. P. Perdew and Y. Wang, Phys. Rev. B 45,
 // 13244 (1992), the published parameters of its fit): e_c(r_s) and v_c = e_c - (r_s/3) de_c/dr_s
 __device__ __forceinline__ double pw92_vc(double rho) {
@@ -250,18 +292,13 @@ extern "C" fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma
   if ((st = fill(x, 0.0, nf, s)) != FE_OK) return st;
   if ((st = fill(vzero, 0.0, nf, s)) != FE_OK) return st;
   if ((st = k_dinv(m, dinv, s)) != FE_OK) return st;
-  auto dot = [&](const double* a, const double* b, double* out_h) -> fe_status {
-    fe_status e = dot1(a, b, nf, scal, scratch, s);
-    if (e != FE_OK) return e;
-    INVDFT_HIP(hipMemcpyAsync(out_h, scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    INVDFT_HIP(hipStreamSynchronize(s));
-    return FE_OK;
-  };
-  double bb = 0.0, rz = 0.0, rr = 0.0, pq = 0.0;
-  if ((st = dot(r, r, &bb)) != FE_OK) return st;
+  double* S = scal;   // the CG scalars (device)
+  if ((st = dot1(r, r, nf, S + kCgBB, scratch, s)) != FE_OK) return st;
   if ((st = k_precond<double>(r, dinv, 1, nf, z, s)) != FE_OK) return st;
   if ((st = copy_bytes(z, p, (size_t)nf * sizeof(double), s)) != FE_OK) return st;
-  if ((st = dot(r, z, &rz)) != FE_OK) return st;
+  if ((st = dot1(r, z, nf, S + 1, scratch, s)) != FE_OK) return st;
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(64), 0, s, S);
+  INVDFT_HIP(hipGetLastError());
   ApplyArgs aa{};
   aa.X = p;
   aa.Y = q;
@@ -269,24 +306,33 @@ extern "C" fe_status poisson_solve(fe_mesh mesh, const double* rho, double sigma
   aa.nv = 1;
   aa.ld = 1;
   aa.alpha = 1.0;
-  int it = 0;
-  double rel = bb > 0.0 ? 1.0 : 0.0;
-  while (bb > 0.0 && it < maxit) {
+  double hs[3] = {1.0, 0.0, 0.0};   // done, iterations, relative residual, as last read
+  auto read_state = [&]() -> fe_status {
+    INVDFT_HIP(hipMemcpyAsync(hs, S + kCgDone, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    INVDFT_HIP(hipStreamSynchronize(s));
+    return FE_OK;
+  };
+  if ((st = read_state()) != FE_OK) return st;
+  const int check_every = 8;   // host looks at the convergence flag this often
+  const unsigned g = grid_for(nf);
+  for (int it = 0; hs[0] == 0.0 && it < maxit; ++it) {
+    const int irz = 1 + (it & 1), inew = 1 + ((it + 1) & 1);
     if ((st = launch_apply(m, aa, FE_F64, s)) != FE_OK) return st;   // q = (K~/2) p
-    if ((st = dot(p, q, &pq)) != FE_OK) return st;
-    const double alpha = rz / pq;
-    if ((st = axpby(alpha, p, 1.0, x, nf, s)) != FE_OK) return st;
-    if ((st = axpby(-alpha, q, 1.0, r, nf, s)) != FE_OK) return st;
-    ++it;
-    if ((st = dot(r, r, &rr)) != FE_OK) return st;
-    rel = std::sqrt(rr / bb);
-    if (rel <= tol) break;
+    if ((st = dot1(p, q, nf, S + kCgPQ, scratch, s)) != FE_OK) return st;
+    hipLaunchKernelGGL(cg_xr_kernel, dim3(g), dim3(256), 0, s, x, r, p, q, S, irz, nf);
+    INVDFT_HIP(hipGetLastError());
+    if ((st = dot1(r, r, nf, S + kCgRR, scratch, s)) != FE_OK) return st;
+    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, s, S, tol);
+    INVDFT_HIP(hipGetLastError());
     if ((st = k_precond<double>(r, dinv, 1, nf, z, s)) != FE_OK) return st;
-    double rz_new = 0.0;
-    if ((st = dot(r, z, &rz_new)) != FE_OK) return st;
-    if ((st = axpby(1.0, z, rz_new / rz, p, nf, s)) != FE_OK) return st;   // p = z + beta p
-    rz = rz_new;
+    if ((st = dot1(r, z, nf, S + inew, scratch, s)) != FE_OK) return st;
+    hipLaunchKernelGGL(cg_p_kernel, dim3(g), dim3(256), 0, s, p, z, S, inew, irz, nf);
+    INVDFT_HIP(hipGetLastError());
+    if ((it + 1) % check_every == 0 && (st = read_state()) != FE_OK) return st;
   }
+  if ((st = read_state()) != FE_OK) return st;
+  const int it = (int)hs[1];
+  const double rel = hs[2];
   hipLaunchKernelGGL(poisson_finish_kernel, dim3(grid_for(nf)), dim3(256), 0, s, m.d_x1, m.d_w1, m.n1, nf, x, mono,
                      phi);
   INVDFT_HIP(hipGetLastError());
