@@ -267,6 +267,9 @@ def main():
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
                          "and f64d paths (default: the block's buffer columns; 0: off). The f64 path always keeps "
                          "the diagonal preconditioner.")
+    ap.add_argument("--deflate-split", action="store_true",
+                    help="let the deflation go beyond 64 columns of [Psi U] (separate sweeps for the rest); by "
+                         "default the driver deflates with at most 64 - (included orbitals) vectors")
     ap.add_argument("--buffer", type=int, default=-1,
                     help="ChFSI buffer columns above the occupied ones (default: the workload's max(4, 0.2 N_occ), "
                          "with the block rounded up to a multiple of 8 columns, at most 64, at zero temperature)")
@@ -439,9 +442,9 @@ def main():
     paths = {
         "f64": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False),
         "f64d": inv.SolverOptions(**common, filter_prec="f64", adjoint_prec="f64", recompute=False,
-                                  deflate=deflate),
+                                  deflate=deflate, deflate_split=args.deflate_split),
         "mixed": inv.SolverOptions(**common, filter_prec="f32", adjoint_prec="f64", switch_tol=args.switch_tol,
-                                   recompute=True, deflate=deflate),
+                                   recompute=True, deflate=deflate, deflate_split=args.deflate_split),
     }
     order = args.paths.split(",")
     for k, name in enumerate(order):

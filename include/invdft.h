@@ -259,7 +259,10 @@ fe_status adjoint_solve(fe_mesh mesh, const double* v, const double* Psi, const 
  *   Ritz vectors of the eigensolve above the occupied ones (a copy of U with
  *   Psi projected out is used, the caller's U is not modified);
  *   theta_h: nbuf host doubles, each strictly greater than every eps_h[i].
- * Other arguments as adjoint_solve. 1 <= nocc, 1 <= nbuf, nocc + nbuf <= 64.
+ * Other arguments as adjoint_solve. 1 <= nocc <= 64, 1 <= nbuf <= 64. When
+ * nocc + nbuf > 64 the fused MINRES sweeps take the first 64 columns of V and
+ * the remaining deflation vectors are applied by separate Gram and update
+ * sweeps (the same preconditioner).
  * The result is held to the same Euclidean bar as adjoint_solve (FP64):
  * ||b_i - (H~ - eps_i) q_i||_2 <= 2 tol ||b_i||_2 for every column. Since the
  * preconditioner's norm weighs the U directions by 1 / (theta_j - eps_i), the

@@ -331,30 +331,38 @@ fe_status fill_t<float>(float* y, int64_t n, hipStream_t s) { return fill_f32(y,
 // vectors are r' = r - U c with c = U^T r kept as small per-column arrays; the fused passes
 // then run with V in place of Psi (pass B's subtraction V (V^T y) is exactly the deflated
 // recurrence), plus four small per-column corrections.
+// Above 64 columns, V = [Psi U] is split: the fused passes take its first 64 columns
+// (Vf = [Psi U_f], nbf = 64 - k0 vectors of U), and the rest U_r (nb - nbf vectors) is handled
+// by separate Gram and update sweeps whose coefficients Gr1 = U_r^T y and Gr2 = U_r^T u also
+// feed the deflation's per-column corrections.
 struct Deflation {
-  double* V;            // [Psi U], N x (k0 + nb)
+  double* V;            // [Psi U(:, 0..nbf)], N x (k0 + nbf), nbf = min(nb, 64 - k0)
   double* U;            // N x nb
-  int nb;
+  int nb, nbf;
   double* theta;        // nb (device)
   double* eps;          // shifts of the current columns (device, k)
   double *cA, *cB, *cC, *tmp;  // nb x k small arrays (device)
+  double *Gr1, *Gr2;    // (nb - nbf) x k: U_r^T y and U_r^T u (device)
 };
 
-// Extra work of a deflated solve with nocc shifts and nb deflation vectors; pw replaces
-// MRWork's projection scratch (V is wider than Psi).
+// Extra work of a deflated solve with k <= 64 shifts and nb <= 64 deflation vectors; pw
+// replaces MRWork's projection scratch (V is wider than Psi).
 Deflation defl_layout(Bump& bp, const Mesh& m, int k, int nb, double** Ucopy, double** pw) {
   Deflation d{};
   *Ucopy = bp.take<double>((size_t)m.nf * nb);
-  d.V = bp.take<double>((size_t)m.nf * (k + nb));
-  d.U = *Ucopy;
   d.nb = nb;
+  d.nbf = std::max(0, std::min(nb, 64 - k));
+  d.V = bp.take<double>((size_t)m.nf * (k + d.nbf));
+  d.U = *Ucopy;
   d.theta = bp.take<double>(64);
   d.eps = bp.take<double>(64);
   d.cA = bp.take<double>(64 * 64);
   d.cB = bp.take<double>(64 * 64);
   d.cC = bp.take<double>(64 * 64);
   d.tmp = bp.take<double>(64 * 64);
-  *pw = bp.take<double>(project_work_bytes(m.nf, 64, 64) / sizeof(double) + 1);
+  d.Gr1 = bp.take<double>(64 * 64);
+  d.Gr2 = bp.take<double>(64 * 64);
+  *pw = bp.take<double>(project_work_bytes(m.nf, 128, 64) / sizeof(double) + 1);
   return d;
 }
 
@@ -413,7 +421,7 @@ fe_status minres_core(const Mesh& m, const double* v, const ProjSet<T>& ps, cons
   } else {
     if constexpr (sizeof(T) == sizeof(double)) {
       Pj = df->V;
-      kp = k0 + df->nb;
+      kp = k0 + df->nbf;
       cR1 = df->cA;
       cR2 = df->cB;
       cN = df->cC;
@@ -428,6 +436,9 @@ fe_status minres_core(const Mesh& m, const double* v, const ProjSet<T>& ps, cons
       if ((st = copy_bytes(R1, R2, blk * sizeof(T), s)) != FE_OK) return st;
       if ((st = k_precond<T>(R1, w.dinv, k, nf, Z, s)) != FE_OK) return st;
       if ((st = project_out(Pj, kp, Z, k, nf, false, w.pw, s)) != FE_OK) return st;
+      if (nb > df->nbf &&
+          (st = project_out_ld(df->U + df->nbf, nb, nb - df->nbf, Z, k, nf, false, w.pw, s)) != FE_OK)
+        return st;
       if ((st = defl_scale(cR1, df->theta, df->eps, k, nb, df->tmp, s)) != FE_OK) return st;
       if ((st = rotate_axpy(df->U, nb, nf, nb, df->tmp, k, 1.0, Z, k, s)) != FE_OK) return st;
     } else {
@@ -472,15 +483,37 @@ fe_status minres_core(const Mesh& m, const double* v, const ProjSet<T>& ps, cons
     if ((st = launch_apply(m, aa, prec, s)) != FE_OK) return st;
     // the orbitals past the fused block leave y first (P = P_f P_r: the two sets are orthogonal)
     if ((st = project_rest(Y, k)) != FE_OK) return st;
+    // the coefficients U_r^T y of the deflation vectors past the fused block (y keeps those
+    // components through pass A: z has components along U, so z.y needs all of y)
+    const int nbr = defl ? df->nb - df->nbf : 0;
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (nbr > 0 && (st = gram(df->U + df->nbf, df->nb, Y, k, nf, nbr, k, false, df->Gr1, w.pw, s)) != FE_OK)
+        return st;
+    }
     // one sweep: G = Psi^T y, z.y, z.r1; alfa = v.(P y - c1 r1) = v.y - c1 v.r1 (v is orthogonal to Psi)
     if ((st = minres_pass_a<T>(Pj, kp, Y, Z, R1, k, nf, fw, s)) != FE_OK) return st;
     if (defl && (st = defl_d2(fw.d2, cR1, cR2, df->theta, df->eps, k, df->nb, s)) != FE_OK) return st;
     if ((st = mr_alfa(w.st, fw.d1, fw.d2, k, it == 1, s)) != FE_OK) return st;
-    if (defl && (st = defl_cnew(fw.G, k0, df->nb, cR1, cR2, w.st, k, cN, s)) != FE_OK) return st;
+    if (defl && (st = defl_cnew(fw.G, k0, df->nbf, df->Gr1, df->nb, cR1, cR2, w.st, k, cN, s)) != FE_OK) return st;
+    // before pass B forms r' = y - V G1 - c1 r1' - c2 r2', y loses its U_r part as well
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (nbr > 0 && (st = rotate_axpy(df->U + df->nbf, df->nb, nf, nbr, df->Gr1, k, -1.0, Y, k, s)) != FE_OK)
+        return st;
+    }
     // r_new = P y - c1 r1 - c2 r2 (into R1) ; u = D^{-1} r_new (into Y) ; G2 = Psi^T u ; beta^2 = r_new.u
     if ((st = minres_pass_b<T>(Pj, kp, Y, R1, R2, w.st, w.dinv, k, nf, fw, s)) != FE_OK) return st;
     if (defl) {
-      if ((st = defl_beta_g2(fw.d, fw.G2, k0, df->nb, cN, df->theta, df->eps, k, s)) != FE_OK) return st;
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (nbr > 0 && (st = gram(df->U + df->nbf, df->nb, Y, k, nf, nbr, k, false, df->Gr2, w.pw, s)) != FE_OK)
+          return st;
+      }
+      if ((st = defl_beta_g2(fw.d, fw.G2, k0, df->nbf, df->Gr2, df->nb, cN, df->theta, df->eps, k, s)) != FE_OK)
+        return st;
+      // u loses U_r (U_r^T u - c_new / (theta - eps)), as pass C does for the vectors inside
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (nbr > 0 && (st = rotate_axpy(df->U + df->nbf, df->nb, nf, nbr, df->Gr2, k, -1.0, Y, k, s)) != FE_OK)
+          return st;
+      }
       double* t = cR1;  // the coefficients follow the vectors: cR1 <- cR2, cR2 <- c_new
       cR1 = cR2;
       cR2 = cN;
@@ -887,10 +920,11 @@ size_t fe_workspace_bytes(fe_mesh mesh, int op, int nv, fe_prec prec) {
     case FE_OP_EIGENSOLVE: eig_layout(bp, m, nv, nv, prec); return bp.off;
     case FE_OP_ADJOINT_SOLVE: adjoint_layout(bp, m, nv, prec); return bp.off;
     case FE_OP_ADJOINT_DEFLATED: {  // nv = nocc + nbuf: a bound for every split of nv
-      if (nv > 64) return 0;
+      if (nv > 128) return 0;
+      const int k = std::min(nv, 64);
       double *u, *pw;
-      mr_layout(bp, m, nv, FE_F64);
-      defl_layout(bp, m, nv, nv, &u, &pw);
+      mr_layout(bp, m, k, FE_F64);
+      defl_layout(bp, m, k, k, &u, &pw);   // U: min(nv, 64) columns; V: min(nv, 64) or more
       return bp.off;
     }
     case FE_OP_LOSS_GRAD:
@@ -1137,8 +1171,8 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
     return fail(FE_EINVAL, "adjoint_solve_deflated: NULL argument");
   if (!aligned16(Psi) || !aligned16(U) || !aligned16(B) || !aligned16(Q) || !aligned16(work))
     return fail(FE_EINVAL, "adjoint_solve_deflated: Psi, U, B, Q and work must be 16-byte aligned");
-  if (nocc < 1 || nbuf < 1 || nocc + nbuf > 64)
-    return fail(FE_EINVAL, "adjoint_solve_deflated: nocc >= 1, nbuf >= 1 and nocc + nbuf <= 64 required");
+  if (nocc < 1 || nocc > 64 || nbuf < 1 || nbuf > 64)
+    return fail(FE_EINVAL, "adjoint_solve_deflated: 1 <= nocc <= 64 and 1 <= nbuf <= 64 required");
   if (!(tol > 0.0) || maxit < 1) return fail(FE_EINVAL, "adjoint_solve_deflated: tol > 0 and maxit >= 1 required");
   double emax = -INFINITY;
   for (int i = 0; i < nocc; ++i) {
@@ -1161,7 +1195,7 @@ fe_status adjoint_solve_deflated(fe_mesh mesh, const double* v, const double* Ps
   if ((st = copy_bytes(U, Uc, (size_t)m.nf * nbuf * sizeof(double), s)) != FE_OK) return st;
   for (int pass = 0; pass < 2; ++pass)
     if ((st = project_out(Psi, nocc, Uc, nbuf, m.nf, false, w.pw, s)) != FE_OK) return st;
-  if ((st = defl_pack(Psi, nocc, Uc, nbuf, df.V, m.nf, s)) != FE_OK) return st;
+  if ((st = defl_pack(Psi, nocc, Uc, nbuf, df.nbf, df.V, m.nf, s)) != FE_OK) return st;
   INVDFT_HIP(hipMemcpyAsync(df.theta, theta_h, nbuf * sizeof(double), hipMemcpyHostToDevice, s));
   return adjoint_f64(m, v, proj_whole(Psi, nocc), eps_h, nocc, B, Q, tol, maxit, iters_h, relres_h, w, &df,
                      "adjoint_solve_deflated", s);

@@ -41,13 +41,17 @@ fe_status k_mask_cols(float* r, const double* rr, const double* bb, double tol, 
 fe_status k_sub_from(const double* b, double* r, int64_t total, hipStream_t s);
 
 // deflated preconditioner of the adjoint (small per-column corrections; krylov.hip)
-fe_status defl_pack(const double* Psi, int k0, const double* U, int nb, double* V, int64_t nf, hipStream_t s);
+// V = [Psi U(:, 0..nb)] (U with row pitch ldu), N x (k0 + nb)
+fe_status defl_pack(const double* Psi, int k0, const double* U, int ldu, int nb, double* V, int64_t nf,
+                    hipStream_t s);
 fe_status defl_d2(double* d2, const double* cR1, const double* cR2, const double* theta, const double* eps, int k,
                   int nb, hipStream_t s);
-fe_status defl_cnew(const double* G1, int k0, int nb, const double* cR1, const double* cR2, const double* st, int k,
-                    double* cnew, hipStream_t s);
-fe_status defl_beta_g2(double* d, double* G2, int k0, int nb, const double* cnew, const double* theta,
-                       const double* eps, int k, hipStream_t s);
+// The U rows of G1 / G2 (from the fused passes, k0 = their Psi width) hold the first nbf
+// deflation vectors; Gr ((nb - nbf) x k) holds the rest, or is unused when nbf == nb.
+fe_status defl_cnew(const double* G1, int k0, int nbf, const double* Gr, int nb, const double* cR1, const double* cR2,
+                    const double* st, int k, double* cnew, hipStream_t s);
+fe_status defl_beta_g2(double* d, double* G2, int k0, int nbf, double* Gr, int nb, const double* cnew,
+                       const double* theta, const double* eps, int k, hipStream_t s);
 fe_status defl_scale(const double* c, const double* theta, const double* eps, int k, int nb, double* out,
                      hipStream_t s);
 

@@ -221,15 +221,15 @@ __global__ void mr_givens_kernel(double* __restrict__ st, const double* __restri
 // P_ext = I - V V^T; the stored Lanczos vectors are r' = r - U c, c = U^T r (nb x k small
 // arrays c[j k + i]); G blocks from the fused passes are (k0 + nb) x k row-major.
 
-// V[a, 0..k0) = Psi[a, :], V[a, k0..k0+nb) = U[a, :]
-__global__ void defl_pack_kernel(const double* __restrict__ Psi, int k0, const double* __restrict__ U, int nb,
-                                 double* __restrict__ V, long long nf) {
+// V[a, 0..k0) = Psi[a, :], V[a, k0..k0+nb) = U[a, 0..nb) (U with row pitch ldu >= nb)
+__global__ void defl_pack_kernel(const double* __restrict__ Psi, int k0, const double* __restrict__ U, int ldu,
+                                 int nb, double* __restrict__ V, long long nf) {
   const int kp = k0 + nb;
   const long long total = nf * kp;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
     const long long a = e / kp;
     const int c = (int)(e % kp);
-    V[e] = c < k0 ? Psi[a * k0 + c] : U[a * nb + (c - k0)];
+    V[e] = c < k0 ? Psi[a * k0 + c] : U[a * ldu + (c - k0)];
   }
 }
 
@@ -243,28 +243,34 @@ __global__ void defl_d2_kernel(double* __restrict__ d2, const double* __restrict
   }
 }
 
-// c_new = U^T y - c1 cR1 - c2 cR2 (U^T y: rows k0.. of G1 from pass A)
-__global__ void defl_cnew_kernel(const double* __restrict__ G1, int k0, int nb, const double* __restrict__ cR1,
-                                 const double* __restrict__ cR2, const double* __restrict__ st, int k,
-                                 double* __restrict__ cnew) {
+// c_new = U^T y - c1 cR1 - c2 cR2. U^T y: rows k0.. of G1 from pass A for the first nbf vectors
+// (those inside the fused passes' block), the rows of Gr for the rest (nb - nbf of them).
+__global__ void defl_cnew_kernel(const double* __restrict__ G1, int k0, int nbf, const double* __restrict__ Gr,
+                                 int nb, const double* __restrict__ cR1, const double* __restrict__ cR2,
+                                 const double* __restrict__ st, int k, double* __restrict__ cnew) {
   for (int e = threadIdx.x; e < nb * k; e += blockDim.x) {
     const int j = e / k, i = e % k;
-    cnew[e] = G1[(k0 + j) * k + i] - st[S_C1 * k + i] * cR1[e] - st[S_C2 * k + i] * cR2[e];
+    const double uy = j < nbf ? G1[(k0 + j) * k + i] : Gr[(j - nbf) * k + i];
+    cnew[e] = uy - st[S_C1 * k + i] * cR1[e] - st[S_C2 * k + i] * cR2[e];
   }
 }
 
-// beta^2 = r'.D^{-1} r' + sum_j c_new^2 / (theta_j - eps_i); the U rows of G2 lose c_new / (theta - eps)
-// so that pass C forms z = P_ext D^{-1} r' + U c_new / (theta - eps)
-__global__ void defl_beta_g2_kernel(double* __restrict__ d, double* __restrict__ G2, int k0, int nb,
-                                    const double* __restrict__ cnew, const double* __restrict__ theta,
-                                    const double* __restrict__ eps, int k) {
+// beta^2 = r'.D^{-1} r' + sum_j c_new^2 / (theta_j - eps_i); the U rows of G2 (and of Gr for the
+// vectors past the fused block) lose c_new / (theta - eps), so that the update with them forms
+// z = P_ext D^{-1} r' + U c_new / (theta - eps)
+__global__ void defl_beta_g2_kernel(double* __restrict__ d, double* __restrict__ G2, int k0, int nbf,
+                                    double* __restrict__ Gr, int nb, const double* __restrict__ cnew,
+                                    const double* __restrict__ theta, const double* __restrict__ eps, int k) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
     double t = 0.0;
     for (int j = 0; j < nb; ++j) {
       const double c = cnew[j * k + i];
       const double g = 1.0 / (theta[j] - eps[i]);
       t += c * c * g;
-      G2[(k0 + j) * k + i] -= c * g;
+      if (j < nbf)
+        G2[(k0 + j) * k + i] -= c * g;
+      else
+        Gr[(j - nbf) * k + i] -= c * g;
     }
     d[i] += t;
   }
@@ -412,8 +418,9 @@ int mr_state_iters() { return S_ITERS; }
 int mr_state_active() { return S_ACTIVE; }
 int mr_state_invbeta() { return S_INVBETA; }
 
-fe_status defl_pack(const double* Psi, int k0, const double* U, int nb, double* V, int64_t nf, hipStream_t s) {
-  hipLaunchKernelGGL(defl_pack_kernel, dim3(grid_for(nf * (k0 + nb))), dim3(256), 0, s, Psi, k0, U, nb, V,
+fe_status defl_pack(const double* Psi, int k0, const double* U, int ldu, int nb, double* V, int64_t nf,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(defl_pack_kernel, dim3(grid_for(nf * (k0 + nb))), dim3(256), 0, s, Psi, k0, U, ldu, nb, V,
                      (long long)nf);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
@@ -426,16 +433,16 @@ fe_status defl_d2(double* d2, const double* cR1, const double* cR2, const double
   return FE_OK;
 }
 
-fe_status defl_cnew(const double* G1, int k0, int nb, const double* cR1, const double* cR2, const double* st, int k,
-                    double* cnew, hipStream_t s) {
-  hipLaunchKernelGGL(defl_cnew_kernel, dim3(1), dim3(256), 0, s, G1, k0, nb, cR1, cR2, st, k, cnew);
+fe_status defl_cnew(const double* G1, int k0, int nbf, const double* Gr, int nb, const double* cR1, const double* cR2,
+                    const double* st, int k, double* cnew, hipStream_t s) {
+  hipLaunchKernelGGL(defl_cnew_kernel, dim3(1), dim3(256), 0, s, G1, k0, nbf, Gr, nb, cR1, cR2, st, k, cnew);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }
 
-fe_status defl_beta_g2(double* d, double* G2, int k0, int nb, const double* cnew, const double* theta,
-                       const double* eps, int k, hipStream_t s) {
-  hipLaunchKernelGGL(defl_beta_g2_kernel, dim3(1), dim3(64), 0, s, d, G2, k0, nb, cnew, theta, eps, k);
+fe_status defl_beta_g2(double* d, double* G2, int k0, int nbf, double* Gr, int nb, const double* cnew,
+                       const double* theta, const double* eps, int k, hipStream_t s) {
+  hipLaunchKernelGGL(defl_beta_g2_kernel, dim3(1), dim3(64), 0, s, d, G2, k0, nbf, Gr, nb, cnew, theta, eps, k);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
 }

@@ -52,6 +52,8 @@ class SolverOptions:
     occ_cut: float = 1e-12           # finite T: orbitals with f_i <= occ_cut * smax are left out
     deflate: int = 0                 # FP64 adjoint: Ritz vectors above the included orbitals that
                                      # deflate its preconditioner (0 = plain diagonal preconditioner)
+    deflate_split: bool = False      # also deflate beyond 64 columns of [Psi U] (separate sweeps:
+                                     # fewer MINRES iterations, each dearer); else at most 64 - n
 
 
 @dataclass
@@ -108,11 +110,12 @@ class InverseProblem:
         if o.deflate > 0:
             if o.adjoint_prec != "f64":
                 raise ValueError("the deflated adjoint solve is FP64 only")
-            # deflation while the orbitals and the deflation vectors fit 64 columns; the plain
-            # solve (wider blocks, or no deflation vector clearing the shifts) in the same buffer
+            # deflation with at most 64 orbitals and 64 deflation vectors; the plain solve (more
+            # orbitals, or no deflation vector clearing the shifts) in the same buffer
             need = mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, "f64")
-            if self.nocc < 64:
-                need = max(need, mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED, min(64, self.nocc + o.deflate), "f64"))
+            if self.nocc <= 64:
+                need = max(need, mesh.workspace_bytes(L.FE_OP_ADJOINT_DEFLATED,
+                                                      self.nocc + min(64, o.deflate), "f64"))
             self.work_adj = api._work(need, dev)
         else:
             self.work_adj = api._work(mesh.workspace_bytes(L.FE_OP_ADJOINT_SOLVE, self.nocc, o.adjoint_prec), dev)
@@ -171,8 +174,8 @@ class InverseProblem:
         j0 = st.n
         while j0 < self.nv and eig[j0] <= top + 1e-8 * max(1.0, abs(top)):
             j0 += 1                                  # degenerate with an included orbital
-        nb = min(self.opts.deflate, self.nv - j0, 64 - st.n)
-        if nb >= 1:
+        nb = min(self.opts.deflate, self.nv - j0, 64 if self.opts.deflate_split else 64 - st.n)
+        if nb >= 1 and st.n <= 64:
             st.U = self.X[:, j0:j0 + nb].contiguous()
             st.theta = list(eig[j0:j0 + nb])
 

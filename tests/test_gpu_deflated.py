@@ -171,10 +171,10 @@ def test_deflated_rejects_bad_input():
     rel = (C.c_double * k)()
     wk = api._work(m.workspace_bytes(_lib.FE_OP_ADJOINT_DEFLATED, 64, "f64"), DEV)
     st = lib.adjoint_solve_deflated(m.handle, api._ptr(v), api._ptr(Psi), api._host_doubles(r.eig[:k]), k,
-                                    api._ptr(U), api._host_doubles([1e3] * 64), 65 - k, api._ptr(B),
+                                    api._ptr(U), api._host_doubles([1e3] * 65), 65, api._ptr(B),
                                     api._ptr(B), 1e-10, 10, its, rel, api._ptr(wk), None)
-    assert st == _lib.FE_EINVAL                              # nocc + nbuf > 64
-    assert m.workspace_bytes(_lib.FE_OP_ADJOINT_DEFLATED, 65, "f64") == 0
+    assert st == _lib.FE_EINVAL                              # nbuf > 64
+    assert m.workspace_bytes(_lib.FE_OP_ADJOINT_DEFLATED, 129, "f64") == 0
 
 
 def test_driver_deflate_option_same_gradient():

@@ -245,3 +245,35 @@ def test_mapped_apply_wide_blocks(nv):
     Y = api.ks_apply(m, torch.tensor(v, device=DEV), torch.tensor(X, device=DEV), shift=shift)
     err = np.abs(Y.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err <= 1e-13, err
+
+
+def test_deflated_split_beyond_64_columns():
+    """50 shifts deflated with 30 vectors: V = [Psi U] has 80 columns, so the fused sweeps take
+    the first 64 and the last 16 deflation vectors go through their own Gram and update sweeps.
+    Same system, so the same solution as the oracle's; fewer iterations than with 14 vectors
+    (which fit the fused block)."""
+    from paper_2510_10529_amd import api
+    om, v, ev, occ, psi, rho, rho_d = _oracle()
+    m = _mesh()
+    k, nb = 50, 30
+    W = om.weights()
+    occ50 = np.full(k, 2.0)
+    psi50 = ev.psi[:, :k]
+    eps = ev.eps[:k]
+    rho50 = ks.density(psi50, occ50, W)
+    B = ks.adjoint_rhs(psi50, occ50, rho50, rho_d)
+    Rr = 4.0 * (rho50 - rho_d)[:, None] * psi50 * occ50[None, :]
+    Qref = ks.adjoint_sum_over_states(ev.eps, ev.psi, k, Rr)
+    Psi = _t(psi50)
+    res = {}
+    for n in (14, nb):
+        Q, ar = api.adjoint_solve(m, _t(v), Psi, list(eps), _t(B), tol=1e-12, maxit=6000,
+                                  U=_t(ev.psi[:, k:k + n]), theta=list(ev.eps[k:k + n]))
+        assert ar.status == 0, (n, ar)
+        assert max(ar.relres) <= 2e-12, (n, max(ar.relres))
+        Qn = Q.cpu().numpy()
+        np.testing.assert_allclose(psi50.T @ Qn, 0, atol=1e-10 * np.abs(Qn).max())
+        err = np.linalg.norm(Qn - Qref, axis=0) / np.linalg.norm(Qref, axis=0)
+        assert err.max() <= 1e-8, (n, err.max())
+        res[n] = max(ar.iters)
+    assert res[nb] < res[14], res
