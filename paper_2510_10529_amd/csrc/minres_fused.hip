@@ -296,6 +296,7 @@ __global__ __launch_bounds__(kThreads) void pass_b_kernel(const T* __restrict__ 
   __shared__ double red[kThreads * Piece<T>::NS * Piece<T>::EPV];
   __shared__ double sd[kTile];
   __shared__ double sC[2][kTile];          // c1, c2 per column
+  __shared__ double sDv[kRows];            // the chunk's rows of D^{-1}
   constexpr int NS = Piece<T>::NS, EPV = Piece<T>::EPV;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -333,18 +334,18 @@ __global__ __launch_bounds__(kThreads) void pass_b_kernel(const T* __restrict__ 
     load_pieces<FULL>(Y + row0 * k, nr * k, sl, yv);
     load_pieces<FULL>(R1 + row0 * k, nr * k, sl, r1v);
     load_pieces<FULL>(R2 + row0 * k, nr * k, sl, r2v);
+    const double drow = threadIdx.x < nr ? dinv[row0 + threadIdx.x] : 0.0;
+    __syncthreads();  // the previous chunk's Gram product is done with sPsi and sPG
+    put_psi(ps, pv, sPsi);
+    if (threadIdx.x < kRows) sDv[threadIdx.x] = drow;
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < NS; ++j)
 #pragma unroll
       for (int m = 0; m < EPV; ++m) {
         const int r = sl.row[j][m];
-        const bool ok = r >= 0 && r < nr;
-        const double d = dinv[row0 + (ok ? r : 0)];
-        dv[j][m] = ok ? d : 0.0;
+        dv[j][m] = (r >= 0 && r < nr) ? sDv[r] : 0.0;
       }
-    __syncthreads();  // the previous chunk's Gram product is done with sPsi and sPG
-    put_psi(ps, pv, sPsi);
-    __syncthreads();
     if (w < TJ) psi_times_g(sPsi, k0, gB, w, li, lk, sPG);
     __syncthreads();
     double rn[NS][EPV], u[NS][EPV];
