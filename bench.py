@@ -73,6 +73,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--kT 0]
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -267,6 +268,8 @@ def main():
                     help="Ritz vectors above the orbitals that deflate the adjoint's preconditioner on the mixed "
                          "and f64d paths (default: the block's buffer columns; 0: off). The f64 path always keeps "
                          "the diagonal preconditioner.")
+    ap.add_argument("--degree", type=int, default=0,
+                    help="Chebyshev filter degree (default: the workload's)")
     ap.add_argument("--deflate-split", action="store_true",
                     help="let the deflation go beyond 64 columns of [Psi U] (separate sweeps for the rest); by "
                          "default the driver deflates with at most 64 - (included orbitals) vectors")
@@ -299,6 +302,8 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     wl = workload(args.config)
+    if args.degree > 0:
+        wl = dataclasses.replace(wl, cheb_degree=args.degree)
     log(f"workload {wl.name}: p={wl.p} n={wl.n} L={wl.half_width} N_e={wl.n_elec}")
     breaks = vxc_vertices(wl.half_width, args.graded, 0.5 * wl.half_width, 1.35) if args.graded > 0 else None
     if args.mapped is not None and (breaks is not None or args.vxc_h > 0 or args.frontend):
