@@ -277,3 +277,18 @@ def test_deflated_split_beyond_64_columns():
         assert err.max() <= 1e-8, (n, err.max())
         res[n] = max(ar.iters)
     assert res[nb] < res[14], res
+
+
+def test_wide_refusals():
+    """FP32-inner adjoint solves and deflation keep their 64-orbital limits."""
+    from paper_2510_10529_amd import _lib, api
+    om, v, ev, occ, psi, rho, rho_d = _oracle()
+    m = _mesh()
+    B = _t(ks.adjoint_rhs(psi, occ, rho, rho_d))
+    with pytest.raises(_lib.FEError) as e:
+        api.adjoint_solve(m, _t(v), _t(psi), list(ev.eps[:NOCC]), B, prec="f32")
+    assert e.value.status == _lib.FE_EINVAL
+    with pytest.raises(_lib.FEError) as e:
+        api.adjoint_solve(m, _t(v), _t(psi), list(ev.eps[:NOCC]), B, U=_t(ev.psi[:, NOCC:NOCC + 8]),
+                          theta=list(ev.eps[NOCC:NOCC + 8]))
+    assert e.value.status == _lib.FE_EINVAL       # more than 64 orbitals with deflation
