@@ -21,10 +21,11 @@
 //      wavefront loads one contiguous 512-byte piece per instruction), in FP64 and FP32;
 //      and a Gershgorin bound of (1/2) W_e^{-1/2} K_e W_e^{-1/2} (Fried's element bound).
 //
-// Apply: Y = alpha cs_j ((K~/2) X + (v - c - s_j) X) + beta Z as one elementwise launch
-// (the diagonal and the Chebyshev term) and eight launches of cell products, one per
-// parity class (ex, ey, ez mod 2): cells of one class share no node, so each launch adds
-// its contributions with plain read-modify-write, in a fixed order, bitwise reproducibly.
+// Apply: Y = alpha cs_j ((K~/2) X + (v - c - s_j) X) + beta Z as eight launches of cell
+// products, one per parity class (ex, ey, ez mod 2): cells of one class share no node, so
+// each launch adds its contributions with plain read-modify-write, in a fixed order, bitwise
+// reproducibly. The first class that holds a node writes it, with the diagonal and Chebyshev
+// terms (X from the gathered block); the later ones add.
 // A workgroup gathers a cell's X_e (n_p x up to 64 columns) into LDS, and each wavefront
 // streams its M-tiles of K~_e from HBM through v_mfma_f64_16x16x4f64, all its tiles at once,
 // with the A fragments two steps ahead in registers (FP32 storage is widened to FP64 there). Up to 64 columns the matrices stream once
@@ -318,26 +319,6 @@ struct MapApply {
   double colshift[kMaxShiftCols];
 };
 
-// Y = alpha cs_j (v - c - s_j) X + beta Z (every free node; Y may alias Z, never X)
-template <typename T>
-__global__ void mapped_diag_kernel(const MapApply a, long long nf) {
-  const T* X = static_cast<const T*>(a.X);
-  T* Y = static_cast<T*>(a.Y);
-  const T* Z = static_cast<const T*>(a.Z);
-  const long long total = nf * a.nv;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long node = e / a.nv;
-    const int j = (int)(e - node * a.nv);
-    const size_t idx = (size_t)node * a.ld + j;
-    const double sh = a.cshift + (a.has_colshift ? a.colshift[j] : 0.0);
-    const double cs = a.alpha * (a.colscale ? a.colscale[j] : 1.0);
-    double y = cs * (a.v[node] - sh) * (double)X[idx];
-    if (Z) y += a.beta * (double)Z[idx];
-    Y[idx] = (T)y;
-  }
-}
-
 // One parity class: workgroup = (cell of the class, chunk of 16 NTL columns). Wavefront w
 // owns the M-tiles w, w + 4, ... (MTI of them) and keeps MTI x NTL independent accumulators,
 // so consecutive MFMAs never wait on each other and every fragment of K~_e loaded from HBM
@@ -356,8 +337,10 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
   constexpr int JP = JC + ((JC == 32 || (JC == 64 && sizeof(T) == 4)) ? 16 : 0);
   __shared__ __attribute__((aligned(16))) T sX[NP4][JP];
   __shared__ long long sNode[NP4];   // free-node index of each local node, -1 at Dirichlet nodes
+  __shared__ unsigned char sFirst[NP4];   // 1: this cell's class is the first launched that holds the node
   const T* X = static_cast<const T*>(a.X);
   T* Y = static_cast<T*>(a.Y);
+  const T* Z = static_cast<const T*>(a.Z);
   const T* K = static_cast<const T*>(a.K);
   const int tid = threadIdx.x;
   const int jc = blockIdx.x % a.jchunks;
@@ -367,12 +350,22 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
   const int pn = P * a.n;
   for (int l = tid; l < NP4; l += NT) {
     long long idx = -1;
+    unsigned char first = 0;
     if (l < NP) {
       const int gx = ex * P + l % P1, gy = ey * P + (l / P1) % P1, gz = ez * P + l / (P1 * P1);
-      if (gx >= 1 && gx <= pn - 1 && gy >= 1 && gy <= pn - 1 && gz >= 1 && gz <= pn - 1)
+      if (gx >= 1 && gx <= pn - 1 && gy >= 1 && gy <= pn - 1 && gz >= 1 && gz <= pn - 1) {
         idx = (gx - 1) + (long long)a.n1 * ((gy - 1) + (long long)a.n1 * (gz - 1));
+        // the classes run in the order (cz, cy, cx) = (0, 0, 0), (0, 0, 1), ...: the first that
+        // holds the node takes, along each axis, the smaller parity of the cells holding it (a
+        // vertex plane lies in two cells, one of each parity)
+        const int px = gx % P == 0 ? 0 : (gx / P) % 2;
+        const int py = gy % P == 0 ? 0 : (gy / P) % 2;
+        const int pz = gz % P == 0 ? 0 : (gz / P) % 2;
+        first = (px == a.cx && py == a.cy && pz == a.cz) ? 1 : 0;
+      }
     }
     sNode[l] = idx;
+    sFirst[l] = first;
   }
   __syncthreads();
   // gather X_e: 16-byte pieces where the row pitch keeps them aligned and inside the block
@@ -442,6 +435,7 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
       const int j = j0 + t * 16 + lr;
       if (j >= a.nv) continue;
       const double cs = a.alpha * (a.colscale ? a.colscale[j] : 1.0);
+      const double sh = a.cshift + (a.has_colshift ? a.colshift[j] : 0.0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + lk + 4 * r;
@@ -449,7 +443,15 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
         const long long node = sNode[row];
         if (node < 0) continue;
         const size_t idx = (size_t)node * a.ld + j;
-        Y[idx] = (T)((double)Y[idx] + cs * acc[i][t][r]);
+        if (sFirst[row]) {
+          // the node's first class also adds the diagonal and Chebyshev terms: Y = alpha cs_j
+          // ((K~/2) X + (v - c - s_j) X) + beta Z (Y may alias Z: Z is read first)
+          double y = cs * (acc[i][t][r] + (a.v[node] - sh) * (double)sX[row][t * 16 + lr]);
+          if (Z) y += a.beta * (double)Z[idx];
+          Y[idx] = (T)y;
+        } else {
+          Y[idx] = (T)((double)Y[idx] + cs * acc[i][t][r]);
+        }
       }
     }
   }
@@ -499,10 +501,6 @@ fe_status launch_cells(const Mesh& m, MapApply& a, hipStream_t s) {
 
 template <typename T>
 fe_status launch_mapped_typed(const Mesh& m, MapApply& a, hipStream_t s) {
-  const long long total = m.nf * a.nv;
-  const unsigned grid = (unsigned)std::min<long long>((total + 255) / 256, 1 << 16);
-  hipLaunchKernelGGL(mapped_diag_kernel<T>, dim3(grid), dim3(256), 0, s, a, (long long)m.nf);
-  INVDFT_HIP(hipGetLastError());
   switch (m.p) {
     case 1: return launch_cells<T, 1>(m, a, s);
     case 2: return launch_cells<T, 2>(m, a, s);
