@@ -72,6 +72,28 @@ def test_apply_matches_oracle(p, nv):
     assert err32 <= 2e-6, err32
 
 
+@pytest.mark.parametrize("p,nv", [(2, 7), (4, 21)])
+def test_chebyshev_filter_matches_oracle(p, nv):
+    """The filter's Chebyshev steps read the previous block Z (beta Z); on a mapped mesh the
+    first parity class holding a node adds it with the diagonal term. Degree 6 against the
+    oracle's recurrence on the assembled operator."""
+    from oracle import chfsi
+    from paper_2510_10529_amd import api
+    n = 4 if p <= 2 else 3
+    m, om = _pair(p, n, 3.0)
+    X = random_block(om.n_free, nv, 31 * p + nv)
+    v = np.random.default_rng(p + 7).uniform(-2, 2, om.n_free)
+    H = fe.hamiltonian_csr(om, v)
+    lam = np.linalg.eigvalsh(H.toarray())
+    a0, b = lam[0] - 0.1, lam[-1] + 0.1
+    a = lam[min(nv, lam.size - 1)]
+    ref = chfsi.filter_apply(lambda Z: H @ Z, X, 6, a, b, a0)
+    Xd = torch.tensor(X, device=DEV)
+    api.cheb_filter(m, torch.tensor(v, device=DEV), 6, a, b, a0, Xd)
+    err = np.abs(Xd.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= 1e-11, err
+
+
 def test_identity_map_equals_uniform_kernel():
     from paper_2510_10529_amd import api
     m0 = api.Mesh(4, 3, 3.0, mapped_amp=0.0)
