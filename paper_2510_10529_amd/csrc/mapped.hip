@@ -28,8 +28,9 @@
 // terms (X from the gathered block); the later ones add.
 // A workgroup gathers a cell's X_e (n_p x up to 64 columns) into LDS, and each wavefront
 // streams its M-tiles of K~_e from HBM through v_mfma_f64_16x16x4f64, all its tiles at once,
-// with the A fragments two steps ahead in registers (FP32 storage is widened to FP64 there). Up to 64 columns the matrices stream once
-// per apply; the product is HBM-bound up to about 32 FP64 columns and FP64-MFMA-bound beyond.
+// with the A fragments three steps ahead in registers (FP32 storage is widened to FP64 there).
+// Up to 64 columns the matrices stream once per apply; the product is HBM-bound up to about 32
+// FP64 columns and FP64-MFMA-bound beyond.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -397,9 +398,10 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
   const T* Km[MTI];
 #pragma unroll
   for (int i = 0; i < MTI; ++i) Km[i] = Kc + (size_t)min(wave + NW * i, MT - 1) * KS * 64;
-  // A fragments two steps ahead in registers (a ring of PFD slots per tile): one step ahead
-  // leaves too few loads in flight to cover HBM latency (measured: 10 % slower at p = 5)
-  constexpr int PFD = 2;
+  // A fragments three steps ahead in registers (a ring of PFD slots per tile): one step ahead
+  // leaves too few loads in flight to cover HBM latency (measured: 10 % slower at p = 5), and
+  // three beat two by 5-7 % at 16 columns
+  constexpr int PFD = 3;
   T an[PFD][MTI];
 #pragma unroll
   for (int d = 0; d < PFD; ++d)
@@ -457,15 +459,16 @@ __global__ __launch_bounds__(NT) void mapped_cell_kernel(const MapApply a) {
   }
 }
 
-// Eight wavefronts instead of four when a cell has 8 or more M-tiles (p >= 4: measured up to
-// 21 % faster at 64 columns, the MFMA-bound case, and 7 % at 16 FP32 columns), when a
-// workgroup's LDS block exceeds 80 KB (one workgroup per CU) or when four wavefronts would each
-// hold more than 8 accumulator tiles.
+// Sixteen wavefronts when a cell has 12 or more M-tiles (p = 5: one tile each, 22 % faster at
+// 64 columns, the MFMA-bound case); eight instead of four when it has 8 or more (p = 4: up to
+// 21 % faster at 64 columns and 7 % at 16 FP32 columns), when a workgroup's LDS block exceeds
+// 80 KB (one workgroup per CU) or when four wavefronts would each hold more than 8 accumulator
+// tiles.
 template <typename T, int P, int NTL>
 fe_status launch_class(MapApply& a, long long grid, hipStream_t s) {
   constexpr int NP = (P + 1) * (P + 1) * (P + 1), NP4 = (NP + 3) / 4 * 4, MT = (NP + 15) / 16;
   constexpr int JC = 16 * NTL, JP = JC + ((JC == 32 || (JC == 64 && sizeof(T) == 4)) ? 16 : 0);
-  constexpr int NT = (MT >= 8 || (size_t)NP4 * JP * sizeof(T) > 80 * 1024 || ((MT + 3) / 4) * NTL > 8) ? 512 : 256;
+  constexpr int NT = MT >= 12 ? 1024 : (MT >= 8 || (size_t)NP4 * JP * sizeof(T) > 80 * 1024 || ((MT + 3) / 4) * NTL > 8) ? 512 : 256;
   hipLaunchKernelGGL((mapped_cell_kernel<T, P, NTL, NT>), dim3((unsigned)grid), dim3(NT), 0, s, a);
   INVDFT_HIP(hipGetLastError());
   return FE_OK;
