@@ -391,6 +391,15 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
     }
   };
 
+  // Column constants of this thread, read once: every x-pass item and z-column of a thread
+  // has the column tid % J (NT is a multiple of J). A global load of them inside the plane
+  // loop would make the wave wait for the plane prefetch in flight as well (memory loads
+  // complete in order), leaving the prefetch nothing to overlap.
+  static_assert(NT % J == 0, "a thread's items share one column");
+  const int jt = j0 + tid % J;
+  const double sh_t = prm.cshift + ((prm.has_colshift && jt < nv) ? prm.colshift[jt] : 0.0);
+  const CT cs_t = (CT)(prm.kscale * prm.alpha) * ((prm.colscale && jt < nv) ? (CT)prm.colscale[jt] : CT(1));
+
   // per-thread z-column accumulators: outputs of the P+1 planes of the current cell
   CT acc[CPT][P1];
 #pragma unroll
@@ -405,7 +414,10 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
   int buf = 0;
 #pragma unroll 1
   for (int gz = gz0; gz <= gz1; ++gz) {
-    if (gz < gz1) load_plane(gz + 1);  // prefetch: in flight during this plane's passes
+    // prefetch, in flight during this plane's passes. Issued and stored on every plane (after
+    // the last, plane 0: zeros, no memory access), so that no load is pending across the
+    // loop's back edge and the next plane's loads do not wait for this plane's stores.
+    load_plane(gz < gz1 ? gz + 1 : 0);
     // ---- x-pass (LDS -> LDS): U1 = M~x X, U2 = K~x X on owned x, all NYI rows; diagonal term
     for (int item = tid; item < NXI; item += NT) {
       const int jj = item % J;
@@ -467,11 +479,9 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
         }
       }
       if (yl >= P && yl < P + BY) {
-        const int j = j0 + jj;
-        const double sh = prm.cshift + ((prm.has_colshift && j < nv) ? prm.colshift[j] : 0.0);
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          sD[buf][yl - P][exl * P + i][jj] = (CT)(prm.dscale * (sV[yl - P][exl * P + i] - sh) * (double)in[P + i]);
+          sD[buf][yl - P][exl * P + i][jj] = (CT)(prm.dscale * (sV[yl - P][exl * P + i] - sh_t) * (double)in[P + i]);
       }
     }
     __syncthreads();
@@ -547,7 +557,7 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       }
     }
     // the raw plane and potential were last read by this plane's x-pass (before the barrier above)
-    if (gz < gz1) store_plane();
+    store_plane();
     __syncthreads();
     // ---- z-step: plane gz is node k of the current cell (k = 0 only for the first plane).
     // The accumulators hold 2 h^2 times the output (unit-cell tables; kscale on output);
@@ -581,32 +591,45 @@ __global__ __launch_bounds__(NT) void ks_apply_kernel(const KParams prm) {
       // cell ez complete: planes ez P + i, i < P, are final
       const int ez = (rel - 1) / P + ezs;
       if (ez >= ez0) {
+        // The outputs replace acc[c][0..P-1] in place. Every load of Z is issued before the
+        // first store, and no load follows a store: memory operations are counted in order,
+        // so a wait for a later load would also wait for every store before it. (Y may alias
+        // Z element for element; each element's Z is read before any store.)
+        const long long pstride = (long long)n1 * n1 * ld;
+        long long obase[CPT];
+        bool ook[CPT];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
           const int col = tid + c * NT;
-          if (col >= NCOL) continue;
           const int jj = col % J;
           const int xl = (col / J) % BX;
           const int yl = col / (J * BX);
           const int gx = ex0 * P + xl, gy = ey0 * P + yl, j = j0 + jj;
-          if (!node_ok(gx) || !node_ok(gy) || j >= nv) continue;
-          const CT scale = (CT)(prm.kscale * prm.alpha) * (prm.colscale ? (CT)prm.colscale[j] : CT(1));
-          const long long base = node_index(gx, gy, 1) * ld + j;
-          const long long pstride = (long long)n1 * n1 * ld;
-          // Y may alias Z: read all of this column's Z values before the first store
-          CT zv[P];
-#pragma unroll
-          for (int i = 0; i < P; ++i) {
-            const int gzo = ez * P + i;
-            zv[i] = (Z && node_ok(gzo)) ? widen<T>(Z[base + (long long)(gzo - 1) * pstride]) : CT(0);
-          }
-#pragma unroll
-          for (int i = 0; i < P; ++i) {
-            const int gzo = ez * P + i;
-            if (!node_ok(gzo)) continue;
-            Y[base + (long long)(gzo - 1) * pstride] = narrow<T>(scale * acc[c][i] + (CT)prm.beta * zv[i]);
-          }
+          ook[c] = col < NCOL && node_ok(gx) && node_ok(gy) && j < nv;
+          obase[c] = ook[c] ? node_index(gx, gy, ez * P) * ld + j : 0;
         }
+        if (Z) {
+          CT zv[CPT][P];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+              zv[c][i] = (ook[c] && node_ok(ez * P + i)) ? widen<T>(Z[obase[c] + i * pstride]) : CT(0);
+#pragma unroll
+          for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] = fma(cs_t, acc[c][i], (CT)prm.beta * zv[c][i]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] *= cs_t;
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            if (ook[c] && node_ok(ez * P + i)) Y[obase[c] + i * pstride] = narrow<T>(acc[c][i]);
       }
       // this vertex plane is also node 0 of the next cell
       if constexpr (!GR) {
@@ -798,6 +821,11 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
   const int yjj = tid % J, yxl = (tid / J) % BX, yey = tid / (J * BX);
   const int ogx = ex0 * P + yxl, oj = j0 + yjj;
   const bool col_ok = yz && node_ok(ogx) && oj < nv;
+  // column constants, read once (every x-pass item of this thread has the column tid % J as
+  // well): a global load inside the plane loop would also wait for the plane prefetch
+  static_assert(NT % J == 0, "a thread's items share one column");
+  const double sh_t = prm.cshift + ((prm.has_colshift && oj < nv) ? prm.colshift[oj] : 0.0);
+  const CT cs_t = (CT)(prm.kscale * prm.alpha) * ((prm.colscale && oj < nv) ? (CT)prm.colscale[oj] : CT(1));
   CT acc[P][P + 1];
 #pragma unroll
   for (int c = 0; c < P; ++c)
@@ -810,7 +838,10 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
   __syncthreads();
 #pragma unroll 1
   for (int gz = gz0; gz <= gz1; ++gz) {
-    if (gz < gz1) load_plane(gz + 1);  // prefetch: in flight during this plane's passes
+    // prefetch, in flight during this plane's passes. Issued and stored on every plane (after
+    // the last, plane 0: zeros, no memory access), so that no load is pending across the
+    // loop's back edge and the next plane's loads do not wait for this plane's stores.
+    load_plane(gz < gz1 ? gz + 1 : 0);
     // ---- x-pass: U1 = M~x X, U2 = K~x X on owned x, all NYI rows; diagonal term of owned nodes
     for (int item = tid; item < NXI; item += NT) {
       const int jj = item % J;
@@ -839,17 +870,16 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
         sU2[yl][exl * P + i][jj] = u2;
       }
       if (yl >= P && yl < P + BY) {
-        const int j = j0 + jj;
-        const double sh = prm.cshift + ((prm.has_colshift && j < nv) ? prm.colshift[j] : 0.0);
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          sD[yl - P][exl * P + i][jj] = (CT)(prm.dscale * (sV[yl - P][exl * P + i] - sh) * (double)in[P + i]);
+          sD[yl - P][exl * P + i][jj] = (CT)(prm.dscale * (sV[yl - P][exl * P + i] - sh_t) * (double)in[P + i]);
       }
     }
     __syncthreads();
     // ---- y-pass and z-step of this thread's y-cell column
     const int rel = gz - gz0;
     const int k = (rel == 0) ? 0 : ((rel - 1) % P) + 1;
+    CT av[P], bv[P];
     if (yz) {
       CT a1[2 * P + 1], a2[2 * P + 1];
 #pragma unroll
@@ -857,7 +887,7 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
         a1[q] = sU1[yey * P + q][yxl][yjj];
         a2[q] = sU2[yey * P + q][yxl][yjj];
       }
-      CT av[P], bv[P], dv[P];
+      CT dv[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         CT A = MT(i, 0) * a1[P], B = MT(i, 0) * a2[P];
@@ -881,42 +911,53 @@ __global__ __launch_bounds__(NT) void ks_apply_yz_kernel(const KParams prm) {
         dv[i] = sD[yey * P + i][yxl][yjj];
       }
       z_accumulate<CT, P, P, NU>(k, cM, cK, acc, av, bv, dv);
-      if (k == P) {
-        const int ez = (rel - 1) / P + ezs;
-        if (ez >= ez0 && col_ok) {
-          const CT scale = (CT)(prm.kscale * prm.alpha) * (prm.colscale ? (CT)prm.colscale[oj] : CT(1));
-          const long long pstride = (long long)n1 * n1 * ld;
+    }
+    // the raw plane and potential were last read by this plane's x-pass (before the barrier
+    // above); storing the prefetched plane before this plane's outputs keeps its wait from
+    // also waiting for the output stores
+    store_plane();
+    if (yz && k == P) {
+      const int ez = (rel - 1) / P + ezs;
+      if (ez >= ez0 && col_ok) {
+        // outputs in place in acc[c][0..P-1]; every load of Z before the first store, no load
+        // after a store (Y may alias Z element for element)
+        const long long pstride = (long long)n1 * n1 * ld;
+        const long long obase = node_index(ogx, ey0 * P + yey * P, ez * P) * ld + oj;
+        const long long rstride = (long long)n1 * ld;
+        if (Z) {
+          CT zv[P][P];
 #pragma unroll
-          for (int c = 0; c < P; ++c) {
-            const int gy = ey0 * P + yey * P + c;
-            if (!node_ok(gy)) continue;
-            const long long base = node_index(ogx, gy, 1) * ld + oj;
-            // Y may alias Z: read all of this column's Z values before the first store
-            CT zv[P];
+          for (int c = 0; c < P; ++c)
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-              const int gzo = ez * P + i;
-              zv[i] = (Z && node_ok(gzo)) ? widen<T>(Z[base + (long long)(gzo - 1) * pstride]) : CT(0);
-            }
+            for (int i = 0; i < P; ++i)
+              zv[c][i] = (node_ok(ey0 * P + yey * P + c) && node_ok(ez * P + i))
+                             ? widen<T>(Z[obase + c * rstride + i * pstride])
+                             : CT(0);
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-              const int gzo = ez * P + i;
-              if (!node_ok(gzo)) continue;
-              Y[base + (long long)(gzo - 1) * pstride] = narrow<T>(scale * acc[c][i] + (CT)prm.beta * zv[i]);
-            }
-          }
+          for (int c = 0; c < P; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] = fma(cs_t, acc[c][i], (CT)prm.beta * zv[c][i]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < P; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] *= cs_t;
         }
 #pragma unroll
-        for (int c = 0; c < P; ++c) {
-          const CT carry = acc[c][P];
+        for (int c = 0; c < P; ++c)
 #pragma unroll
-          for (int i = 0; i <= P; ++i)
-            acc[c][i] = fma(KT(i, 0), av[c], fma(MT(i, 0), bv[c], i == 0 ? carry : CT(0)));
-        }
+          for (int i = 0; i < P; ++i)
+            if (node_ok(ey0 * P + yey * P + c) && node_ok(ez * P + i))
+              Y[obase + c * rstride + i * pstride] = narrow<T>(acc[c][i]);
+      }
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const CT carry = acc[c][P];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+          acc[c][i] = fma(KT(i, 0), av[c], fma(MT(i, 0), bv[c], i == 0 ? carry : CT(0)));
       }
     }
-    // the raw plane and potential were last read by this plane's x-pass (before the barrier above)
-    if (gz < gz1) store_plane();
     __syncthreads();
   }
 }
