@@ -148,49 +148,87 @@ int gram_blocks(long long N) {
 // device), Xin/out: N x nout (ldo). Each wave owns 16 rows and all nout (<= 64) columns, nin <= 64;
 // out may alias Xin, and A too: a wave reads all of its rows of A before it writes them.
 template <typename T>
-__global__ __launch_bounds__(256) void rotate_kernel(const T* A, int lda, long long N, int nin,
-                                                     const double* __restrict__ C, int ldc, int nout, double alpha,
-                                                     double beta, const T* Xin, T* out, int ldo) {
+__global__ __launch_bounds__(256) void rotate_kernel(
+    const T* A, int lda, long long N, int nin, const double* __restrict__ C, int ldc, int nout, double alpha,
+    double beta, const T* Xin, T* out, int ldo) {
   __shared__ double sC[64 * 64];
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int k = e / 64, j = e % 64;
-    sC[e] = (k < nin && j < nout) ? C[(long long)k * ldc + j] : 0.0;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const long long r0 = ((long long)blockIdx.x * 4 + wave) * 16;
-  if (r0 >= N) return;
   const int li = lane & 15, lk = lane >> 4;
+  // D[i = row][j = out col] = sum_k A[row][k] C[k][j] in 16 MFMA steps of 4 k each. Step s takes
+  // k = 8 (s / 2) + 2 lk + s % 2 in lane group lk, so that a lane's operands of steps 2q and
+  // 2q + 1 are two adjacent entries of its row of A: 8 pieces of 2 per lane, all loads in flight
+  // together, issued before C is staged (one load and one wait per step would leave the kernel
+  // bound by memory latency). Pieces outside A read row 0, column 0 and are discarded.
+  const long long ra = r0 + li;
+  const bool raok = ra < N;
+  const T* Arow = A + (raok ? ra : 0) * lda;
+  double av[16];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k = 8 * q + 2 * lk;
+    const double x0 = ld_d(Arow + (k < nin ? k : 0));
+    const double x1 = ld_d(Arow + (k + 1 < nin ? k + 1 : 0));
+    av[2 * q] = (raok && k < nin) ? x0 : 0.0;
+    av[2 * q + 1] = (raok && k + 1 < nin) ? x1 : 0.0;
+  }
+  {
+    double cv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int k = e / 64, j = e % 64;
+      cv[i] = (k < nin && j < nout) ? C[(long long)k * ldc + j] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sC[threadIdx.x + 256 * i] = cv[i];
+  }
+  __syncthreads();
+  if (r0 >= N) return;
   const int tiles = (nout + 15) / 16;
   d4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
-  // D[i = row][j = out col] = sum_k A[row][k] C[k][j]; A operand lane holds A[r0 + li][k0 + lk]
-  const long long ra = r0 + li;
-  const bool raok = ra < N;
-  for (int k0 = 0; k0 < nin; k0 += 4) {
-    const int k = k0 + lk;
-    const double av = (raok && k < nin) ? ld_d(A + ra * lda + k) : 0.0;
+  // a fixed sequence of 64 products: the zero operands past nin and nout cost nothing that
+  // matters in a kernel bound by memory, and the sequence needs no branches
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < tiles) acc[t] = mfma16(av, sC[(k < 64 ? k : 0) * 64 + 16 * t + li], acc[t]);
-    }
+  for (int st = 0; st < 16; ++st) {
+    const int k = 8 * (st / 2) + 2 * lk + st % 2;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma16(av[st], sC[k * 64 + 16 * t + li], acc[t]);
   }
+  // Output: every load of Xin before the first store (loads and stores complete in order: a
+  // load after a store would wait for it); the empty asm keeps each value's arithmetic here
+  // rather than in the conditional store below. A and Xin may alias out: both are read first.
+  double val[4][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= tiles) continue;
-    const int j = 16 * t + li;
-    if (j >= nout) continue;
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
+      const int j = 16 * t + li;
       const long long row = r0 + lk + 4 * rr;
-      if (row >= N) continue;
-      double val = alpha * acc[t][rr];
-      if (beta != 0.0) val += beta * ld_d(Xin + row * ldo + j);
-      out[row * ldo + j] = (T)val;
+      const bool ok = t < tiles && j < nout && row < N;
+      const double x = beta != 0.0 ? ld_d(Xin + (ok ? row * ldo + j : 0)) : 0.0;
+      val[t][rr] = ok ? x : 0.0;
     }
-  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double v = alpha * acc[t][rr];
+      if (beta != 0.0) v += beta * val[t][rr];
+      asm volatile("" : "+v"(v));
+      val[t][rr] = v;
+    }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int j = 16 * t + li;
+      const long long row = r0 + lk + 4 * rr;
+      if (t < tiles && j < nout && row < N) out[row * ldo + j] = (T)val[t][rr];
+    }
 }
 
 // Column dot products: partial[blk][j] = sum over the block's rows of X[r][j] Y[r][j].
