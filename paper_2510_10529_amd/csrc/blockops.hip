@@ -63,28 +63,37 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(const T* __r
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
 
   const bool symtile = sym && (i0 == j0);
-  // each wave takes every 4th group of 4 rows
-  for (long long r0 = r_begin + 4 * wave; r0 < r_end; r0 += 4 * (kGramThreads / 64)) {
-    const long long r = r0 + lk;
-    const bool rok = r < r_end;
-    double av[4], bv[4];
-    double wr = 1.0;
-    if constexpr (WEIGHTED) wr = rok ? wa[r] - wb[r] : 0.0;
+  // Each wave takes every 4th group of 4 rows, GU groups per trip: the loads of all GU groups are
+  // issued before their products, so that a trip waits for memory once (one group per trip leaves
+  // the kernel bound by memory latency). The rows accumulate in the same order either way.
+  constexpr int GU = 8;
+  constexpr long long kStride = 4 * (kGramThreads / 64);
+  for (long long rb = r_begin + 4 * wave; rb < r_end; rb += GU * kStride) {
+    double av[GU][4], bv[GU][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int ci = i0 + 16 * t + li;
-      const int cj = j0 + 16 * t + li;
-      av[t] = (rok && ci < nx) ? ld_d(X + r * ldx + ci) : 0.0;
-      if constexpr (WEIGHTED) av[t] *= wr;
-      bv[t] = (rok && cj < ny) ? ld_d(Y + r * ldy + cj) : 0.0;
+    for (int g = 0; g < GU; ++g) {
+      const long long r = rb + g * kStride + lk;
+      const bool rok = r < r_end;
+      double wr = 1.0;
+      if constexpr (WEIGHTED) wr = rok ? wa[r] - wb[r] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ci = i0 + 16 * t + li;
+        const int cj = j0 + 16 * t + li;
+        av[g][t] = (rok && ci < nx) ? ld_d(X + r * ldx + ci) : 0.0;
+        if constexpr (WEIGHTED) av[g][t] *= wr;
+        bv[g][t] = (rok && cj < ny) ? ld_d(Y + r * ldy + cj) : 0.0;
+      }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int g = 0; g < GU; ++g)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (symtile && b < a) continue;
-        acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
-      }
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (symtile && b < a) continue;
+          acc[a][b] = mfma16(av[g][a], bv[g][b], acc[a][b]);
+        }
   }
   // reduce the 4 waves through LDS in a fixed order
   for (int w = 0; w < kGramThreads / 64; ++w) {
