@@ -156,7 +156,7 @@ int gram_blocks(long long N) {
 // out = alpha * (A C) + beta * Xin  over N rows; A: N x nin (lda), C: nin x nout (row stride ldc,
 // device), Xin/out: N x nout (ldo). Each wave owns 16 rows and all nout (<= 64) columns, nin <= 64;
 // out may alias Xin, and A too: a wave reads all of its rows of A before it writes them.
-template <typename T>
+template <typename T, int KQ, int TT>
 __global__ __launch_bounds__(256) void rotate_kernel(
     const T* A, int lda, long long N, int nin, const double* __restrict__ C, int ldc, int nout, double alpha,
     double beta, const T* Xin, T* out, int ldo) {
@@ -165,17 +165,19 @@ __global__ __launch_bounds__(256) void rotate_kernel(
   const int wave = threadIdx.x >> 6;
   const long long r0 = ((long long)blockIdx.x * 4 + wave) * 16;
   const int li = lane & 15, lk = lane >> 4;
-  // D[i = row][j = out col] = sum_k A[row][k] C[k][j] in 16 MFMA steps of 4 k each. Step s takes
+  // D[i = row][j = out col] = sum_k A[row][k] C[k][j] in 2 KQ MFMA steps of 4 k each (nin <= 8 KQ)
+  // on TT output tiles of 16 columns (nout <= 16 TT), both fixed at compile time so that the
+  // unrolled products carry no branches and narrow blocks do no padding work. Step s takes
   // k = 8 (s / 2) + 2 lk + s % 2 in lane group lk, so that a lane's operands of steps 2q and
-  // 2q + 1 are two adjacent entries of its row of A: 8 pieces of 2 per lane, all loads in flight
+  // 2q + 1 are two adjacent entries of its row of A: KQ pieces of 2 per lane, all loads in flight
   // together, issued before C is staged (one load and one wait per step would leave the kernel
   // bound by memory latency). Pieces outside A read row 0, column 0 and are discarded.
   const long long ra = r0 + li;
   const bool raok = ra < N;
   const T* Arow = A + (raok ? ra : 0) * lda;
-  double av[16];
+  double av[2 * KQ];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < KQ; ++q) {
     const int k = 8 * q + 2 * lk;
     const double x0 = ld_d(Arow + (k < nin ? k : 0));
     const double x1 = ld_d(Arow + (k + 1 < nin ? k + 1 : 0));
@@ -195,34 +197,31 @@ __global__ __launch_bounds__(256) void rotate_kernel(
   }
   __syncthreads();
   if (r0 >= N) return;
-  const int tiles = (nout + 15) / 16;
-  d4 acc[4];
+  d4 acc[TT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
-  // a fixed sequence of 64 products: the zero operands past nin and nout cost nothing that
-  // matters in a kernel bound by memory, and the sequence needs no branches
+  for (int t = 0; t < TT; ++t) acc[t] = d4{0, 0, 0, 0};
 #pragma unroll
-  for (int st = 0; st < 16; ++st) {
+  for (int st = 0; st < 2 * KQ; ++st) {
     const int k = 8 * (st / 2) + 2 * lk + st % 2;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = mfma16(av[st], sC[k * 64 + 16 * t + li], acc[t]);
+    for (int t = 0; t < TT; ++t) acc[t] = mfma16(av[st], sC[k * 64 + 16 * t + li], acc[t]);
   }
   // Output: every load of Xin before the first store (loads and stores complete in order: a
   // load after a store would wait for it); the empty asm keeps each value's arithmetic here
   // rather than in the conditional store below. A and Xin may alias out: both are read first.
-  double val[4][4];
+  double val[TT][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TT; ++t)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int j = 16 * t + li;
       const long long row = r0 + lk + 4 * rr;
-      const bool ok = t < tiles && j < nout && row < N;
+      const bool ok = j < nout && row < N;
       const double x = beta != 0.0 ? ld_d(Xin + (ok ? row * ldo + j : 0)) : 0.0;
       val[t][rr] = ok ? x : 0.0;
     }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TT; ++t)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       double v = alpha * acc[t][rr];
@@ -231,13 +230,40 @@ __global__ __launch_bounds__(256) void rotate_kernel(
       val[t][rr] = v;
     }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TT; ++t)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int j = 16 * t + li;
       const long long row = r0 + lk + 4 * rr;
-      if (t < tiles && j < nout && row < N) out[row * ldo + j] = (T)val[t][rr];
+      if (j < nout && row < N) out[row * ldo + j] = (T)val[t][rr];
     }
+}
+
+// rotate_kernel instantiated for the block's widths: nin <= 8 KQ (KQ = 2, 4, 8), nout <= 16 TT
+template <typename T, int KQ, int TT>
+void launch_rotate_t(unsigned grid, const T* A, int lda, long long N, int nin, const double* C, int ldc, int nout,
+                     double alpha, double beta, const T* Xin, T* out, int ldo, hipStream_t s) {
+  hipLaunchKernelGGL((rotate_kernel<T, KQ, TT>), dim3(grid), dim3(256), 0, s, A, lda, N, nin, C, ldc, nout, alpha, beta,
+                     Xin, out, ldo);
+}
+
+template <typename T, int KQ>
+void launch_rotate_k(unsigned grid, const T* A, int lda, long long N, int nin, const double* C, int ldc, int nout,
+                     double alpha, double beta, const T* Xin, T* out, int ldo, hipStream_t s) {
+  switch ((nout + 15) / 16) {
+    case 1: launch_rotate_t<T, KQ, 1>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s); break;
+    case 2: launch_rotate_t<T, KQ, 2>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s); break;
+    case 3: launch_rotate_t<T, KQ, 3>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s); break;
+    default: launch_rotate_t<T, KQ, 4>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s); break;
+  }
+}
+
+template <typename T>
+void launch_rotate(unsigned grid, const T* A, int lda, long long N, int nin, const double* C, int ldc, int nout,
+                   double alpha, double beta, const T* Xin, T* out, int ldo, hipStream_t s) {
+  if (nin <= 16) launch_rotate_k<T, 2>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s);
+  else if (nin <= 32) launch_rotate_k<T, 4>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s);
+  else launch_rotate_k<T, 8>(grid, A, lda, N, nin, C, ldc, nout, alpha, beta, Xin, out, ldo, s);
 }
 
 // Column dot products: partial[blk][j] = sum over the block's rows of X[r][j] Y[r][j].
@@ -475,9 +501,8 @@ fe_status rotate_tiled(const T* A, int lda, int64_t N, int nin, const double* C,
     for (int k0 = 0; k0 < nin; k0 += 64) {
       const int nk = std::min(64, nin - k0);
       const bool first = k0 == 0;
-      hipLaunchKernelGGL(rotate_kernel<T>, dim3(grid), dim3(256), 0, s, A + k0, lda, (long long)N, nk,
-                         C + (long long)k0 * ldc + j0, ldc, nj, alpha, first ? beta : 1.0,
-                         first ? (Xin ? Xin + j0 : nullptr) : out + j0, out + j0, ldo);
+      launch_rotate<T>(grid, A + k0, lda, (long long)N, nk, C + (long long)k0 * ldc + j0, ldc, nj, alpha,
+                       first ? beta : 1.0, first ? (Xin ? Xin + j0 : nullptr) : out + j0, out + j0, ldo, s);
       INVDFT_HIP(hipGetLastError());
     }
   }
